@@ -1,0 +1,215 @@
+"""Benchmark of the RL-JSDE hot path on one MI355X.
+
+Workload: a 512x512 synthetic grey image (sinusoids + polygons on a 128
+base), three-quarter-sampled through a random recurrent 4x4-sensor-pixel
+opaque-quadrant tile; window 32, block 4, 100 iterations, rho 0.7, gamma 0.5.
+A step is one reconstruction of the whole frame by the FP32 batched path
+(persistent kernel replayed from its HIP graph). The plain FP64 GPU path is
+timed on the same input beside it, and the FP64 CPU oracle on a bounded
+sample of windows.
+
+Prints one JSON line (see the README for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from synth import make_case  # noqa: E402
+
+W, B, ITERS, RHO, GAMMA = 32, 4, 100, 0.7, 0.5
+ROWS = COLS = 512
+PERIOD = 4
+FLOPS_PER_FREQ_ITER = 30          # factorised form: projection 18, metric 4, update 8
+PEAK_FP32_VALU = 157.3e12         # MI355X FP32 vector peak (packed), FLOP/s
+KERNEL_SOURCES = ["paper_2205_02646_amd/csrc/ljsde_kernels.hip", "paper_2205_02646_amd/csrc/ljsde_internal.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(nwin: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "persistent_f32_512x512_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def _oracle_worker(args):
+    y, tile, blocks = args
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from oracle import ljsde_oracle as O
+    try:
+        from threadpoolctl import threadpool_limits
+        ctx = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        ctx = None
+    out = O.reconstruct(y, tile, W=W, B=B, iters=ITERS, rho=RHO, gamma=GAMMA, form="RL", blocks=blocks)
+    if ctx is not None:
+        ctx.unregister()
+    return [(bi, bj, out[B * bi:B * bi + B, B * bj:B * bj + B]) for bi, bj in blocks]
+
+
+def cpu_baseline(y, tile, n_windows: int, seed: int = 1):
+    """Time the FP64 oracle (RL-JSDE form) on a random sample of windows over
+    the host cores; returns (record, {block: output})."""
+    import multiprocessing as mp
+    rng = np.random.default_rng(seed)
+    nbi, nbj = 2 * y.shape[0] // B, 2 * y.shape[1] // B
+    flat = rng.choice(nbi * nbj, size=n_windows, replace=False)
+    blocks = [divmod(int(f), nbj) for f in np.sort(flat)]
+    cores = min(os.cpu_count() or 1, 16)
+    # group by block row so that workers share per-class precompute
+    chunks = [blocks[k::cores] for k in range(cores)]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        parts = pool.map(_oracle_worker, [(y, tile, c) for c in chunks if c])
+    dt = time.perf_counter() - t0
+    res = {(bi, bj): blk for part in parts for bi, bj, blk in part}
+    mps = n_windows * B * B / dt / 1e6
+    rec = {"value": mps, "unit": "MP/s", "cores": cores, "kind": "oracle",
+           "sample": f"{n_windows} random windows ({n_windows * B * B} px) of the 512x512 frame, "
+                     f"RL-JSDE form (dense per-class B, C, D), {dt:.1f} s wall on {cores} processes "
+                     f"with 1 BLAS thread each"}
+    return rec, res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--oracle-windows", type=int, default=512)
+    ap.add_argument("--no-oracle", action="store_true")
+    ap.add_argument("--profile-copy", action="store_true",
+                    help="also run a plain device copy of known size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(windows are independent; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    case = make_case(ROWS, COLS, PERIOD, seed=0)
+    y64, tile, clean = case["y"], case["tile"], case["clean"]
+
+    oracle_rec, oracle_blocks = (None, {})
+    if not args.no_oracle:
+        oracle_rec, oracle_blocks = cpu_baseline(y64, tile, args.oracle_windows)
+
+    import torch
+    from paper_2205_02646_amd import ljsde
+
+    dev = torch.device("cuda:0")
+    y32 = torch.from_numpy(y64.astype(np.float32)).to(dev)
+    y64d = torch.from_numpy(y64).to(dev)
+    p32 = ljsde.plan(tile, window=W, block=B, iters=ITERS, rho=RHO, gamma=GAMMA)
+    p64 = ljsde.plan(tile, window=W, block=B, iters=ITERS, rho=RHO, gamma=GAMMA, fp64=True)
+    out32 = torch.empty((ROWS, COLS), dtype=torch.float32, device=dev)
+    out64 = torch.empty((ROWS, COLS), dtype=torch.float64, device=dev)
+    jobs = [(y32, p32, out32)]
+    stream = torch.cuda.current_stream()
+
+    def step32():
+        ljsde.reconstruct_batch(jobs, stream=stream)
+
+    def step64():
+        ljsde.reconstruct(y64d, p64, out=out64, stream=stream)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps  # ms per step
+
+    if args.profile_copy:
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    ms32 = timed(step32, args.steps, args.warmup)
+    ms64 = timed(step64, max(3, args.steps // 4), 1)
+    ljsde.synchronize(stream)
+
+    o32 = out32.cpu().numpy().astype(np.float64)
+    o64 = out64.cpu().numpy()
+    mp = ROWS * COLS / 1e6
+    nwin = (ROWS // B) * (COLS // B)
+
+    def psnr(a):
+        return float(10 * np.log10(255.0 ** 2 / np.mean((a - clean) ** 2)))
+
+    quality = {"psnr_fp32_db": psnr(o32), "psnr_fp64_db": psnr(o64),
+               "psnr_delta_fp32_vs_fp64_db": abs(psnr(o32) - psnr(o64)),
+               "maxabs_fp32_vs_fp64": float(np.max(np.abs(o32 - o64)))}
+    if oracle_blocks:
+        e32 = max(float(np.max(np.abs(o32[B * i:B * i + B, B * j:B * j + B] - blk)))
+                  for (i, j), blk in oracle_blocks.items())
+        e64 = max(float(np.max(np.abs(o64[B * i:B * i + B, B * j:B * j + B] - blk)))
+                  for (i, j), blk in oracle_blocks.items())
+        quality.update({"maxabs_fp32_vs_oracle_sample": e32, "maxabs_fp64_vs_oracle_sample": e64,
+                        "oracle_sample_windows": len(oracle_blocks)})
+
+    flops = nwin * ITERS * W * W * FLOPS_PER_FREQ_ITER
+    achieved = flops / (ms32 * 1e-3)
+    value = mp / (ms32 * 1e-3)
+    rec = {
+        "metric": "reconstructed MP/s (FP32 batched vs FP64 plain, same GPU) at <=0.01 dB PSNR delta",
+        "value": value,
+        "unit": "MP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "RL-JSDE 512x512 frame, recurrent 4x4-sensor pattern, W=32 B=4, "
+                               "100 iterations, rho 0.7, gamma 0.5 (FP32 persistent batched launch)",
+                   "rows": ROWS, "cols": COLS, "pattern_period": PERIOD, "window": W, "block": B,
+                   "iters": ITERS, "windows": nwin},
+        "fp64_plain": {"value": mp / (ms64 * 1e-3), "unit": "MP/s", "ms_per_step": ms64},
+        "speedup_fp32_batched_vs_fp64_plain": ms64 / ms32,
+        "quality": quality,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
+                     "traffic": load_traffic(nwin), "kernel_hash": kernel_hash()},
+        "cpu_baseline": oracle_rec,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

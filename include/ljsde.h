@@ -1,0 +1,190 @@
+/*
+ * ljsde.h -- C ABI of the MI355X (gfx950) RL-JSDE reconstruction library.
+ *
+ * RL-JSDE reconstructs an image on a grid of twice the sensor resolution from
+ * three-quarter-sampling measurements (Sec. II, eq. (1)): every sensor pixel
+ * integrates the three transparent quadrants of its 2x2 footprint; the fourth
+ * (the opaque quadrant) is given per pixel by a recurrent pattern. Every
+ * B x B target block is modelled on its surrounding W x W window by a sparse
+ * Fourier model built one coefficient at a time (Sec. III; Sec. IV eqs.
+ * (11)-(18)); only the central block of each window is written out.
+ *
+ * Conventions shared by all entry points
+ *  - Return value: 0 (LJSDE_OK) on success, a negative LJSDE_E* code on
+ *    failure. ljsde_last_error() then describes the failure; the text is
+ *    thread-local and valid until the next call from the same thread.
+ *  - Images are row-major [row][col]. A sensor image of R x C pixels yields a
+ *    reconstruction of 2R x 2C pixels.
+ *  - Pattern codes: o = 2*a + b in {0,1,2,3}, where (a, b) is the (row, col)
+ *    position of the opaque quadrant inside the 2x2 footprint. Sensor pixel
+ *    (i, j) uses pattern[(i % pat_rows) * pat_cols + (j % pat_cols)].
+ *  - Device pointers are HIP device addresses on the current device; the
+ *    caller owns them and keeps them alive until the stream work completes.
+ *    `stream` is a hipStream_t (NULL = the default stream). Reconstruction
+ *    calls are asynchronous; errors raised by a running kernel surface at the
+ *    next call or at ljsde_synchronize().
+ *  - The library owns its plan tables until ljsde_release(); it never frees
+ *    or synchronises caller memory.
+ *  - All entry points are safe to call from several host threads; calls that
+ *    use the same plan on different streams may run concurrently.
+ */
+#ifndef LJSDE_H
+#define LJSDE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+enum {
+    LJSDE_OK = 0,
+    LJSDE_EINVAL = -1,       /* invalid argument (checked on the host, before any GPU work) */
+    LJSDE_EUNSUPPORTED = -2, /* valid for the method, but no kernel for this shape */
+    LJSDE_ENOMEM = -3,       /* host or device allocation failed */
+    LJSDE_EHIP = -4,         /* HIP runtime error, including "no device" */
+    LJSDE_EBADID = -5        /* unknown or released pattern id */
+};
+
+/* plan flags */
+enum {
+    LJSDE_FP64 = 1,           /* FP64 everywhere: measurements/out are double */
+    LJSDE_FP32 = 2,           /* FP32 state and projections; FP64 tables, step and energy;
+                                 measurements/out are float */
+    LJSDE_DFT_SPLITBF16 = 4,  /* FP32 plans: window DFT on MFMA with 3-term split-BF16
+                                 products and FP32 accumulation */
+    LJSDE_Q_ONES = 8          /* frequency weight q = 1 (test mode) */
+};
+
+/*
+ * ljsde_plan -- validate and register a reconstruction plan.
+ *
+ * Defines the local measurement matrices of a recurrent three-quarter
+ * sampling sensor (Sec. II, Sec. IV: all windows with the same local
+ * measurement matrix share their precomputed tables).
+ *  pattern   host, pat_rows x pat_cols uint8 codes (copied; the caller keeps
+ *            ownership). A non-recurrent sensor passes the whole sensor.
+ *  window    W, model window side in high-resolution pixels (Sec. III);
+ *            even, (W - B) divisible by 4. Kernels exist for W in {16, 32}.
+ *  block     B, target block side (Sec. III); even; kernels exist for B in
+ *            {4, 8} with B <= W.
+ *  iters     nu_max >= 1, model-generation iterations per window (Sec. IV).
+ *  rho       spatial weight base of w_m = rho^d (eq. (8)), 0 < rho <= 1.
+ *  gamma     orthogonality deficiency compensation gamma_odc of eq. (15),
+ *            0 < gamma < 2.
+ *  flags     exactly one of LJSDE_FP64 / LJSDE_FP32, plus options.
+ * Returns a pattern id >= 0, or a negative status. Needs no GPU: tables for
+ * an image size are built and uploaded on its first reconstruction.
+ */
+int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols,
+               int window, int block, int iters, double rho, double gamma,
+               unsigned flags);
+
+/*
+ * ljsde_set_energy_floor -- optional stopping test (Sec. IV: iterate up to
+ * nu_max). A window stops early once its weighted residual energy (eq. (8)),
+ * tracked in FP64, falls to tau times its initial value. tau = 0 (default)
+ * disables the test. 0 <= tau < 1.
+ */
+int ljsde_set_energy_floor(int pattern_id, double tau);
+
+/*
+ * ljsde_reconstruct -- reconstruct one image (Sec. IV eqs. (11)-(18) per
+ * target block).
+ *  measurements  device, sensor_rows x sensor_cols, float (FP32 plan) or
+ *                double (FP64 plan). Sides must be multiples of B/2.
+ *  out           device, (2*sensor_rows) x (2*sensor_cols), same dtype;
+ *                every pixel is written.
+ *  stream        hipStream_t or NULL.
+ * FP64 plans run one launch with one wavefront per window; FP32 plans run
+ * the persistent batched kernel with a batch of one.
+ */
+int ljsde_reconstruct(const void *measurements, int sensor_rows, int sensor_cols,
+                      int pattern_id, void *out, void *stream);
+
+/*
+ * ljsde_reconstruct_diag -- as ljsde_reconstruct, and also records the
+ * selected frequency sigma*W + rho of every iteration (eq. (11)).
+ *  selections  device int16, [n_windows][iters] with windows in row-major
+ *              block order (n_windows = (2R/B) * (2C/B)); entries after an
+ *              early stop are -1.
+ */
+int ljsde_reconstruct_diag(const void *measurements, int sensor_rows, int sensor_cols,
+                           int pattern_id, void *out, int16_t *selections, void *stream);
+
+/* one image of a batch */
+typedef struct {
+    const void *measurements; /* device, as for ljsde_reconstruct */
+    int sensor_rows;
+    int sensor_cols;
+    int pattern_id;           /* FP32 plans with equal window, block and iters */
+    void *out;                /* device */
+} ljsde_job;
+
+/*
+ * ljsde_reconstruct_batch -- reconstruct many images of uneven size and
+ * pattern in one persistent launch, captured once as a HIP graph per batch
+ * shape and replayed afterwards. All jobs must use FP32 plans with the same
+ * window, block and iteration count. `jobs` is host memory, read during the
+ * call only.
+ */
+int ljsde_reconstruct_batch(const ljsde_job *jobs, int n_jobs, void *stream);
+
+/*
+ * ljsde_autotune -- time the launch variants of the persistent kernel
+ * (windows per workgroup, work-chunk size) on this batch and keep the
+ * fastest for later batch calls of the same shape class. Results are cached
+ * in memory and, if LJSDE_TUNE_CACHE names a file, in that JSON file.
+ * Synchronises `stream`. Outputs of the batch are overwritten.
+ */
+int ljsde_autotune(const ljsde_job *jobs, int n_jobs, void *stream);
+
+/* ljsde_synchronize -- wait for `stream`; reports pending HIP errors. */
+int ljsde_synchronize(void *stream);
+
+/* ljsde_release -- free a plan's tables; later use of the id -> LJSDE_EBADID. */
+int ljsde_release(int pattern_id);
+
+/* ljsde_last_error -- text of the last failure on this thread ("" if none). */
+const char *ljsde_last_error(void);
+
+/*
+ * Host-side introspection (no GPU needed).
+ *
+ * ljsde_class_count -- number of distinct local measurement matrices (Sec.
+ * IV: B, C and D are shared by all windows with the same one) for an image
+ * of sensor_rows x sensor_cols, and the class of every window:
+ *  class_of_window  host int32 [n_windows] in row-major block order, or NULL.
+ * Returns the class count (>= 1) or a negative status.
+ */
+int ljsde_class_count(int pattern_id, int sensor_rows, int sensor_cols,
+                      int32_t *class_of_window);
+
+/*
+ * ljsde_class_tables -- the FP64 tables of one class, as used on the GPU.
+ *  S      host double [Ws*Ws][4][2] or NULL: weighted-mask spectra
+ *         S_o(k, l) = sum over the class's present sensor pixels (i', j') with
+ *         code o of w(i', j') exp(-2 pi i (i' k + j' l) / Ws), Ws = W/2
+ *         (the factorised form of C, eq. (14)); index [k*Ws + l][o][re, im].
+ *  D      host double [W*W] or NULL: the normaliser of eq. (13).
+ *  codes  host int8 [Ws*Ws] or NULL: pattern code per local sensor pixel,
+ *         -1 where the pixel lies outside the image.
+ */
+int ljsde_class_tables(int pattern_id, int sensor_rows, int sensor_cols, int class_index,
+                       double *S, double *D, int8_t *codes);
+
+/*
+ * ljsde_plan_info -- the geometry of a plan (any output pointer may be NULL):
+ * window W, block B, iterations nu_max and the flags it was created with.
+ */
+int ljsde_plan_info(int pattern_id, int *window, int *block, int *iters, unsigned *flags);
+
+/* ljsde_version -- ABI version (major * 10000 + minor * 100 + patch). */
+int ljsde_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LJSDE_H */

@@ -1,0 +1,885 @@
+// Host runtime of the RL-JSDE library: plan registry, argument validation,
+// enumeration of local measurement matrices ("classes"), FP64 precompute of
+// the per-class tables, device upload and kernel launches.
+//
+// Sec. IV of the paper precomputes B, C and D once per local measurement
+// matrix and reuses them for every window with the same one. For
+// three-quarter sampling all of C factorises through four weighted-mask
+// spectra S_o (one per opaque-quadrant orientation), so a class costs a few
+// tens of KiB instead of the dense C of W^4 complex entries.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/ljsde.h"
+#include "ljsde_internal.h"
+
+namespace ljsde {
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int ok() {
+    g_last_error.clear();
+    return LJSDE_OK;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(e_ == hipErrorOutOfMemory ? LJSDE_ENOMEM : LJSDE_EHIP, "%s: %s", \
+                        #expr, hipGetErrorString(e_));                                    \
+    } while (0)
+
+inline int pmod(int a, int m) {
+    int r = a % m;
+    return r < 0 ? r + m : r;
+}
+
+// Pending simulated allocation failure (test hook, environment LJSDE_FAULT=alloc).
+bool fault_alloc() {
+    const char *f = getenv("LJSDE_FAULT");
+    return f && strcmp(f, "alloc") == 0;
+}
+
+struct AxisKey {
+    int phase, lo, hi;
+    bool operator<(const AxisKey &o) const {
+        return std::tie(phase, lo, hi) < std::tie(o.phase, o.lo, o.hi);
+    }
+};
+
+// Tables of one image size for one plan.
+struct SizeSet {
+    int Ms = 0, Ns = 0, nbi = 0, nbj = 0;
+    std::vector<AxisKey> rowkeys, colkeys;
+    std::vector<int> rowcls, colcls;  // per block row / column
+    int n_classes() const { return (int)(rowkeys.size() * colkeys.size()); }
+    // host FP64 tables (built on demand)
+    bool host_built = false;
+    std::vector<unsigned char> blob;  // n_classes * layout.stride bytes
+    std::vector<double> D;            // n_classes * W * W, normaliser of eq. (13)
+    // device copies
+    int device = -1;
+    unsigned char *d_tables = nullptr;
+    int *d_rowcls = nullptr;
+    int *d_colcls = nullptr;
+};
+
+struct Plan {
+    std::vector<uint8_t> pattern;
+    int pr = 0, pc = 0, W = 0, B = 0, Ws = 0, iters = 0;
+    double rho = 0, gamma = 0, tau = 0;
+    unsigned flags = 0;
+    ClassLayout lay{};
+    std::vector<double> w, ew, dft, q;  // class-independent FP64 tables
+    int device = -1;
+    double *d_consts = nullptr;         // w | ew | dft
+    std::map<std::pair<int, int>, std::unique_ptr<SizeSet>> sizes;
+    bool fp64() const { return (flags & LJSDE_FP64) != 0; }
+};
+
+std::mutex g_mu;
+std::vector<std::unique_ptr<Plan>> g_plans;
+
+ClassLayout make_layout(int W, int Ws) {
+    ClassLayout L{};
+    auto al = [](int x) { return (x + 255) & ~255; };
+    int off = 0;
+    L.offS = off;
+    off = al(off + Ws * Ws * 4 * 2 * (int)sizeof(double));
+    L.offQD64 = off;
+    off = al(off + W * W * (int)sizeof(double));
+    L.offInvD = off;
+    off = al(off + W * W * (int)sizeof(double));
+    L.offQD32 = off;
+    off = al(off + W * W * (int)sizeof(float));
+    L.offCodes = off;
+    off = al(off + Ws * Ws);
+    L.stride = off;
+    return L;
+}
+
+// Class-independent tables: spatial weights (eq. (8)), frequency weights
+// q, and the twiddles of the W-point basis (Sec. III) and of the Ws-point
+// sensor-grid DFT.
+void build_constants(Plan &p) {
+    const int W = p.W, Ws = p.Ws;
+    p.w.resize(Ws * Ws);
+    const double c = (W - 1) / 2.0;
+    for (int i = 0; i < Ws; ++i)
+        for (int j = 0; j < Ws; ++j) {
+            const double di = 2 * i + 0.5 - c, dj = 2 * j + 0.5 - c;
+            p.w[i * Ws + j] = std::pow(p.rho, std::sqrt(di * di + dj * dj));
+        }
+    p.ew.resize(2 * W);
+    for (int k = 0; k < W; ++k) {
+        const double a = 2.0 * M_PI * k / W;
+        p.ew[2 * k] = std::cos(a);
+        p.ew[2 * k + 1] = std::sin(a);
+    }
+    p.dft.resize(2 * Ws);
+    for (int k = 0; k < Ws; ++k) {
+        const double a = -2.0 * M_PI * k / Ws;
+        p.dft[2 * k] = std::cos(a);
+        p.dft[2 * k + 1] = std::sin(a);
+    }
+    p.q.resize(W * W);
+    const double qmax = std::sqrt(2.0) * W / 2.0;
+    for (int s = 0; s < W; ++s)
+        for (int r = 0; r < W; ++r) {
+            if (p.flags & LJSDE_Q_ONES) {
+                p.q[s * W + r] = 1.0;
+                continue;
+            }
+            const double st = std::min(s, W - s), rt = std::min(r, W - r);
+            const double x = 1.0 - std::sqrt(st * st + rt * rt) / qmax;
+            p.q[s * W + r] = x * x;
+        }
+}
+
+AxisKey axis_key(const Plan &p, int b, int Msens, int period) {
+    const int s0 = (p.B * b - (p.W - p.B) / 2) / 2;  // window's first sensor row
+    AxisKey k;
+    k.lo = std::max(0, -s0);
+    k.hi = std::max(0, s0 + p.Ws - Msens);
+    k.phase = pmod(s0, period);
+    return k;
+}
+
+void enumerate(const Plan &p, SizeSet &s) {
+    s.nbi = 2 * s.Ms / p.B;
+    s.nbj = 2 * s.Ns / p.B;
+    std::map<AxisKey, int> rk, ck;
+    s.rowcls.resize(s.nbi);
+    s.colcls.resize(s.nbj);
+    for (int b = 0; b < s.nbi; ++b) {
+        AxisKey k = axis_key(p, b, s.Ms, p.pr);
+        auto it = rk.find(k);
+        if (it == rk.end()) {
+            it = rk.emplace(k, (int)s.rowkeys.size()).first;
+            s.rowkeys.push_back(k);
+        }
+        s.rowcls[b] = it->second;
+    }
+    for (int b = 0; b < s.nbj; ++b) {
+        AxisKey k = axis_key(p, b, s.Ns, p.pc);
+        auto it = ck.find(k);
+        if (it == ck.end()) {
+            it = ck.emplace(k, (int)s.colkeys.size()).first;
+            s.colkeys.push_back(k);
+        }
+        s.colcls[b] = it->second;
+    }
+}
+
+// Per-class FP64 tables. With a_m(sigma, rho) = exp(i theta (2i' sigma + 2j' rho)) H_o(sigma, rho)
+// the diagonal of C (eq. (13)) is D = sum_o |H_o|^2 S_o(0, 0).
+void build_class(const Plan &p, const SizeSet &s, int cls, unsigned char *dst, double *Dout) {
+    const int W = p.W, Ws = p.Ws;
+    const AxisKey &rk = s.rowkeys[cls / (int)s.colkeys.size()];
+    const AxisKey &ck = s.colkeys[cls % (int)s.colkeys.size()];
+    std::vector<int> code(Ws * Ws);
+    for (int i = 0; i < Ws; ++i)
+        for (int j = 0; j < Ws; ++j) {
+            const bool valid = i >= rk.lo && i < Ws - rk.hi && j >= ck.lo && j < Ws - ck.hi;
+            code[i * Ws + j] =
+                valid ? p.pattern[pmod(rk.phase + i, p.pr) * p.pc + pmod(ck.phase + j, p.pc)] : -1;
+        }
+    // S_o(k, l) = sum_{i, j: code = o} w e^{-2 pi i (i k + j l) / Ws}, separable
+    std::vector<double> A(4 * Ws * Ws * 2, 0.0);  // [o][i][l][re, im]
+    for (int o = 0; o < 4; ++o)
+        for (int i = 0; i < Ws; ++i)
+            for (int l = 0; l < Ws; ++l) {
+                double re = 0, im = 0;
+                for (int j = 0; j < Ws; ++j) {
+                    if (code[i * Ws + j] != o) continue;
+                    const int t = (j * l) % Ws;
+                    re += p.w[i * Ws + j] * p.dft[2 * t];
+                    im += p.w[i * Ws + j] * p.dft[2 * t + 1];
+                }
+                A[((o * Ws + i) * Ws + l) * 2] = re;
+                A[((o * Ws + i) * Ws + l) * 2 + 1] = im;
+            }
+    double *S = (double *)(dst + p.lay.offS);
+    for (int k = 0; k < Ws; ++k)
+        for (int l = 0; l < Ws; ++l)
+            for (int o = 0; o < 4; ++o) {
+                double re = 0, im = 0;
+                for (int i = 0; i < Ws; ++i) {
+                    const int t = (i * k) % Ws;
+                    const double ar = A[((o * Ws + i) * Ws + l) * 2], ai = A[((o * Ws + i) * Ws + l) * 2 + 1];
+                    re += ar * p.dft[2 * t] - ai * p.dft[2 * t + 1];
+                    im += ar * p.dft[2 * t + 1] + ai * p.dft[2 * t];
+                }
+                S[((k * Ws + l) * 4 + o) * 2] = re;
+                S[((k * Ws + l) * 4 + o) * 2 + 1] = im;
+            }
+    double mass[4];
+    for (int o = 0; o < 4; ++o) mass[o] = S[o * 2];  // S_o(0, 0)
+    double *qd = (double *)(dst + p.lay.offQD64);
+    double *inv = (double *)(dst + p.lay.offInvD);
+    float *qd32 = (float *)(dst + p.lay.offQD32);
+    for (int sg = 0; sg < W; ++sg)
+        for (int rh = 0; rh < W; ++rh) {
+            const double eur = p.ew[2 * sg], eui = p.ew[2 * sg + 1];
+            const double evr = p.ew[2 * rh], evi = p.ew[2 * rh + 1];
+            const int uv = (sg + rh) % W;
+            const double hbr = (1 + eur) * (1 + evr) - eui * evi;
+            const double hbi = (1 + eur) * evi + eui * (1 + evr);
+            const double Hr[4] = {hbr - 1.0, hbr - evr, hbr - eur, hbr - p.ew[2 * uv]};
+            const double Hi[4] = {hbi, hbi - evi, hbi - eui, hbi - p.ew[2 * uv + 1]};
+            double D = 0;
+            for (int o = 0; o < 4; ++o) D += (Hr[o] * Hr[o] + Hi[o] * Hi[o]) * mass[o];
+            const int f = sg * W + rh;
+            Dout[f] = D;
+            const bool pos = D > 0;
+            qd[f] = pos ? p.q[f] / D : 0.0;
+            inv[f] = pos ? 1.0 / D : 0.0;
+            qd32[f] = (float)qd[f];
+        }
+    signed char *cd = (signed char *)(dst + p.lay.offCodes);
+    for (int m = 0; m < Ws * Ws; ++m) cd[m] = (signed char)code[m];
+}
+
+void build_host_tables(const Plan &p, SizeSet &s) {
+    if (s.host_built) return;
+    const int n = s.n_classes();
+    s.blob.assign((size_t)n * p.lay.stride, 0);
+    s.D.assign((size_t)n * p.W * p.W, 0.0);
+    for (int c = 0; c < n; ++c)
+        build_class(p, s, c, s.blob.data() + (size_t)c * p.lay.stride, s.D.data() + (size_t)c * p.W * p.W);
+    s.host_built = true;
+}
+
+int get_plan(int id, Plan **out) {
+    if (id < 0 || id >= (int)g_plans.size() || !g_plans[id])
+        return fail(LJSDE_EBADID, "unknown or released pattern id %d", id);
+    *out = g_plans[id].get();
+    return LJSDE_OK;
+}
+
+int check_size(const Plan &p, int Ms, int Ns) {
+    if (Ms <= 0 || Ns <= 0) return fail(LJSDE_EINVAL, "sensor size %dx%d must be positive", Ms, Ns);
+    if ((2 * Ms) % p.B || (2 * Ns) % p.B)
+        return fail(LJSDE_EINVAL, "sensor size %dx%d: sides must be multiples of block/2 = %d", Ms, Ns,
+                    p.B / 2);
+    if ((long long)Ms * Ns > (1LL << 31) / 4)
+        return fail(LJSDE_EUNSUPPORTED, "sensor size %dx%d too large", Ms, Ns);
+    return LJSDE_OK;
+}
+
+int get_size(Plan &p, int Ms, int Ns, SizeSet **out) {
+    int st = check_size(p, Ms, Ns);
+    if (st) return st;
+    auto key = std::make_pair(Ms, Ns);
+    auto it = p.sizes.find(key);
+    if (it == p.sizes.end()) {
+        auto s = std::make_unique<SizeSet>();
+        s->Ms = Ms;
+        s->Ns = Ns;
+        enumerate(p, *s);
+        it = p.sizes.emplace(key, std::move(s)).first;
+    }
+    *out = it->second.get();
+    return LJSDE_OK;
+}
+
+int current_device(int *dev) {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) return fail(LJSDE_EHIP, "no HIP device available");
+    HIP_TRY(hipGetDevice(dev));
+    return LJSDE_OK;
+}
+
+int dev_alloc(void **p, size_t bytes) {
+    if (fault_alloc()) return fail(LJSDE_ENOMEM, "simulated device allocation failure");
+    HIP_TRY(hipMalloc(p, bytes));
+    return LJSDE_OK;
+}
+
+int ensure_device(Plan &p, SizeSet &s) {
+    int dev = 0;
+    int st = current_device(&dev);
+    if (st) return st;
+    if (p.d_consts && p.device != dev)
+        return fail(LJSDE_EUNSUPPORTED, "plan tables live on device %d, current device is %d", p.device,
+                    dev);
+    if (!p.d_consts) {
+        std::vector<double> c;
+        c.insert(c.end(), p.w.begin(), p.w.end());
+        c.insert(c.end(), p.ew.begin(), p.ew.end());
+        c.insert(c.end(), p.dft.begin(), p.dft.end());
+        void *d = nullptr;
+        st = dev_alloc(&d, c.size() * sizeof(double));
+        if (st) return st;
+        hipError_t e = hipMemcpy(d, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return fail(LJSDE_EHIP, "upload of constants: %s", hipGetErrorString(e));
+        }
+        p.d_consts = (double *)d;
+        p.device = dev;
+    }
+    if (!s.d_tables) {
+        build_host_tables(p, s);
+        void *dt = nullptr, *dr = nullptr, *dc = nullptr;
+        st = dev_alloc(&dt, s.blob.size());
+        if (st) return st;
+        st = dev_alloc(&dr, s.rowcls.size() * sizeof(int));
+        if (st) {
+            (void)hipFree(dt);
+            return st;
+        }
+        st = dev_alloc(&dc, s.colcls.size() * sizeof(int));
+        if (st) {
+            (void)hipFree(dt);
+            (void)hipFree(dr);
+            return st;
+        }
+        hipError_t e = hipMemcpy(dt, s.blob.data(), s.blob.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(dr, s.rowcls.data(), s.rowcls.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(dc, s.colcls.data(), s.colcls.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(dt);
+            (void)hipFree(dr);
+            (void)hipFree(dc);
+            return fail(LJSDE_EHIP, "upload of class tables: %s", hipGetErrorString(e));
+        }
+        s.d_tables = (unsigned char *)dt;
+        s.d_rowcls = (int *)dr;
+        s.d_colcls = (int *)dc;
+        s.device = dev;
+    }
+    return LJSDE_OK;
+}
+
+KParams make_params(const Plan &p) {
+    KParams k{};
+    k.W = p.W;
+    k.B = p.B;
+    k.off = (p.W - p.B) / 2;
+    k.iters = p.iters;
+    k.gamma = p.gamma;
+    k.ecoef = 2 * p.gamma - p.gamma * p.gamma;
+    k.tau = p.tau;
+    k.c.w = p.d_consts;
+    k.c.ew = p.d_consts + p.w.size();
+    k.c.dft = p.d_consts + p.w.size() + p.ew.size();
+    k.lay = p.lay;
+    return k;
+}
+
+KJob make_job(const SizeSet &s, const void *y, void *out, int16_t *sel, long long win_begin) {
+    KJob j{};
+    j.y = y;
+    j.out = out;
+    j.tables = s.d_tables;
+    j.rowcls = s.d_rowcls;
+    j.colcls = s.d_colcls;
+    j.sel = sel;
+    j.Ms = s.Ms;
+    j.Ns = s.Ns;
+    j.nbi = s.nbi;
+    j.nbj = s.nbj;
+    j.ncolk = (int)s.colkeys.size();
+    j.win_begin = win_begin;
+    return j;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched launches
+// ---------------------------------------------------------------------------
+
+struct TuneChoice {
+    int waves_per_block = 1;
+    int chunk = 2;
+};
+
+struct BatchState {
+    std::vector<std::tuple<int, int, int>> shape;  // (pattern id, Ms, Ns)
+    std::vector<KJob> host_jobs;
+    KJob *d_jobs = nullptr;
+    unsigned int *d_counter = nullptr;
+    long long total = 0;
+    KParams params{};
+    int ws = 16;
+    int device = -1;
+    TuneChoice choice;
+    int grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~BatchState() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (d_jobs) (void)hipFree(d_jobs);
+        if (d_counter) (void)hipFree(d_counter);
+    }
+};
+
+std::map<std::string, std::unique_ptr<BatchState>> g_batches;
+std::map<std::string, TuneChoice> g_tuned;
+hipStream_t g_capture_stream = nullptr;
+
+std::string tune_key(const Plan &p, long long total_windows, int n_classes) {
+    hipDeviceProp_t prop{};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipGetDeviceProperties(&prop, dev);
+    int bucket = 0;
+    while ((1 << bucket) < n_classes) ++bucket;
+    int wb = 0;
+    while ((1LL << wb) < total_windows) ++wb;
+    std::ostringstream os;
+    os << prop.gcnArchName << "/W" << p.W << "/B" << p.B << "/it" << p.iters << "/fp32/c" << bucket
+       << "/n" << wb;
+    return os.str();
+}
+
+void load_tune_cache() {
+    static bool loaded = false;
+    if (loaded) return;
+    loaded = true;
+    const char *path = getenv("LJSDE_TUNE_CACHE");
+    if (!path) return;
+    std::ifstream f(path);
+    if (!f) return;
+    std::string line;
+    // one entry per line: "key" : [waves_per_block, chunk]
+    while (std::getline(f, line)) {
+        size_t a = line.find('"'), b = line.find('"', a + 1), l = line.find('[', b), r = line.find(']', l);
+        if (a == std::string::npos || b == std::string::npos || l == std::string::npos ||
+            r == std::string::npos)
+            continue;
+        TuneChoice c;
+        if (sscanf(line.c_str() + l + 1, "%d , %d", &c.waves_per_block, &c.chunk) == 2 &&
+            (c.waves_per_block == 1 || c.waves_per_block == 2 || c.waves_per_block == 4) && c.chunk >= 1 &&
+            c.chunk <= 64)
+            g_tuned[line.substr(a + 1, b - a - 1)] = c;
+    }
+}
+
+void save_tune_cache() {
+    const char *path = getenv("LJSDE_TUNE_CACHE");
+    if (!path) return;
+    std::ofstream f(path);
+    if (!f) return;
+    f << "{\n";
+    size_t i = 0;
+    for (auto &kv : g_tuned) {
+        f << "  \"" << kv.first << "\" : [" << kv.second.waves_per_block << ", " << kv.second.chunk << "]"
+          << (++i < g_tuned.size() ? "," : "") << "\n";
+    }
+    f << "}\n";
+}
+
+int grid_for(int ws, const TuneChoice &c, int *grid) {
+    int dev = 0, ncu = 0, blocks = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    int e = persistent_blocks_per_cu(ws, c.waves_per_block, &blocks);
+    if (e != 0 || blocks <= 0) return fail(LJSDE_EHIP, "occupancy query failed (%d)", e);
+    *grid = ncu * blocks;
+    return LJSDE_OK;
+}
+
+// Builds (or finds) the batch state for this shape, refreshes the device job
+// table if the buffers changed, and returns it.
+int prepare_batch(const ljsde_job *jobs, int n, void *stream, BatchState **out) {
+    if (!jobs || n <= 0) return fail(LJSDE_EINVAL, "empty batch");
+    Plan *p0 = nullptr;
+    int st = get_plan(jobs[0].pattern_id, &p0);
+    if (st) return st;
+    std::ostringstream key;
+    for (int i = 0; i < n; ++i) {
+        Plan *p = nullptr;
+        st = get_plan(jobs[i].pattern_id, &p);
+        if (st) return st;
+        if (p->fp64()) return fail(LJSDE_EUNSUPPORTED, "job %d: batched launches need FP32 plans", i);
+        if (p->W != p0->W || p->B != p0->B || p->iters != p0->iters || p->gamma != p0->gamma ||
+            p->tau != p0->tau)
+            return fail(LJSDE_EINVAL, "job %d: all plans of a batch need equal window, block, iters, "
+                                      "gamma and energy floor", i);
+        if (!jobs[i].measurements || !jobs[i].out)
+            return fail(LJSDE_EINVAL, "job %d: null device pointer", i);
+        st = check_size(*p, jobs[i].sensor_rows, jobs[i].sensor_cols);
+        if (st) return st;
+        key << jobs[i].pattern_id << ':' << jobs[i].sensor_rows << 'x' << jobs[i].sensor_cols << ';';
+    }
+    int dev = 0;
+    st = current_device(&dev);
+    if (st) return st;
+    key << "@" << dev;
+    auto &slot = g_batches[key.str()];
+    if (!slot) {
+        auto b = std::make_unique<BatchState>();
+        long long total = 0;
+        int n_classes = 0;
+        for (int i = 0; i < n; ++i) {
+            Plan *p = nullptr;
+            get_plan(jobs[i].pattern_id, &p);
+            SizeSet *s = nullptr;
+            st = get_size(*p, jobs[i].sensor_rows, jobs[i].sensor_cols, &s);
+            if (st) return st;
+            st = ensure_device(*p, *s);
+            if (st) return st;
+            b->host_jobs.push_back(make_job(*s, nullptr, nullptr, nullptr, total));
+            total += (long long)s->nbi * s->nbj;
+            n_classes = std::max(n_classes, s->n_classes());
+        }
+        if (total >= (1LL << 31)) return fail(LJSDE_EUNSUPPORTED, "batch has too many windows");
+        b->total = total;
+        b->params = make_params(*p0);
+        b->ws = p0->Ws;
+        b->device = dev;
+        st = dev_alloc((void **)&b->d_jobs, sizeof(KJob) * n);
+        if (st) return st;
+        st = dev_alloc((void **)&b->d_counter, sizeof(unsigned int));
+        if (st) return st;
+        load_tune_cache();
+        auto t = g_tuned.find(tune_key(*p0, total, n_classes));
+        if (t != g_tuned.end()) b->choice = t->second;
+        st = grid_for(b->ws, b->choice, &b->grid);
+        if (st) return st;
+        slot = std::move(b);
+    }
+    BatchState *b = slot.get();
+    bool changed = false;
+    for (int i = 0; i < n; ++i) {
+        KJob &j = b->host_jobs[i];
+        if (j.y != jobs[i].measurements || j.out != jobs[i].out) {
+            j.y = jobs[i].measurements;
+            j.out = jobs[i].out;
+            changed = true;
+        }
+    }
+    if (changed) {
+        if (stream) HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+        HIP_TRY(hipMemcpy(b->d_jobs, b->host_jobs.data(), sizeof(KJob) * n, hipMemcpyHostToDevice));
+    }
+    *out = b;
+    return LJSDE_OK;
+}
+
+int launch_batch_eager(BatchState &b, const TuneChoice &c, int grid, void *stream) {
+    int e = launch_reset_counter(b.d_counter, stream);
+    if (e) return fail(LJSDE_EHIP, "reset launch: %s", hipGetErrorString((hipError_t)e));
+    e = launch_persistent_f32(b.params, b.d_jobs, (int)b.host_jobs.size(), b.total, b.d_counter, b.ws,
+                              c.waves_per_block, c.chunk, grid, stream);
+    if (e) return fail(LJSDE_EHIP, "persistent launch: %s", hipGetErrorString((hipError_t)e));
+    return LJSDE_OK;
+}
+
+int capture_graph(BatchState &b) {
+    if (!g_capture_stream) HIP_TRY(hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking));
+    if (b.exec) {
+        (void)hipGraphExecDestroy(b.exec);
+        b.exec = nullptr;
+    }
+    if (b.graph) {
+        (void)hipGraphDestroy(b.graph);
+        b.graph = nullptr;
+    }
+    HIP_TRY(hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal));
+    int st = launch_batch_eager(b, b.choice, b.grid, g_capture_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(g_capture_stream, &g);
+    if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(LJSDE_EHIP, "graph capture: %s", hipGetErrorString(e));
+    b.graph = g;
+    HIP_TRY(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
+    return LJSDE_OK;
+}
+
+int run_batch(const ljsde_job *jobs, int n, void *stream) {
+    BatchState *b = nullptr;
+    int st = prepare_batch(jobs, n, stream, &b);
+    if (st) return st;
+    if (!b->exec) {
+        st = capture_graph(*b);
+        if (st) return st;
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream));
+    return ok();
+}
+
+}  // namespace
+}  // namespace ljsde
+
+using namespace ljsde;
+
+extern "C" {
+
+int ljsde_version(void) { return 10000; }
+
+int ljsde_plan_info(int pattern_id, int *window, int *block, int *iters, unsigned *flags) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *p = nullptr;
+    int st = get_plan(pattern_id, &p);
+    if (st) return st;
+    if (window) *window = p->W;
+    if (block) *block = p->B;
+    if (iters) *iters = p->iters;
+    if (flags) *flags = p->flags;
+    return ok();
+}
+
+const char *ljsde_last_error(void) { return g_last_error.c_str(); }
+
+int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, int block, int iters,
+               double rho, double gamma, unsigned flags) {
+    if (!pattern) return fail(LJSDE_EINVAL, "pattern is null");
+    if (pat_rows <= 0 || pat_cols <= 0)
+        return fail(LJSDE_EINVAL, "pattern size %dx%d must be positive", pat_rows, pat_cols);
+    if ((long long)pat_rows * pat_cols > (1LL << 28)) return fail(LJSDE_EINVAL, "pattern too large");
+    for (long long i = 0; i < (long long)pat_rows * pat_cols; ++i)
+        if (pattern[i] > 3) return fail(LJSDE_EINVAL, "pattern code %d at %lld not in 0..3", pattern[i], i);
+    if (window <= 0 || block <= 0 || window % 2 || block % 2 || block > window || (window - block) % 4)
+        return fail(LJSDE_EINVAL,
+                    "window %d / block %d: need even sizes, block <= window, (window - block) %% 4 == 0",
+                    window, block);
+    if (iters < 1) return fail(LJSDE_EINVAL, "iters %d must be >= 1", iters);
+    if (!(rho > 0.0 && rho <= 1.0)) return fail(LJSDE_EINVAL, "rho %g must be in (0, 1]", rho);
+    if (!(gamma > 0.0 && gamma < 2.0)) return fail(LJSDE_EINVAL, "gamma %g must be in (0, 2)", gamma);
+    const unsigned known = LJSDE_FP64 | LJSDE_FP32 | LJSDE_DFT_SPLITBF16 | LJSDE_Q_ONES;
+    if (flags & ~known) return fail(LJSDE_EINVAL, "unknown flags 0x%x", flags & ~known);
+    if (((flags & LJSDE_FP64) != 0) == ((flags & LJSDE_FP32) != 0))
+        return fail(LJSDE_EINVAL, "exactly one of LJSDE_FP64 / LJSDE_FP32 is required");
+    if ((flags & LJSDE_DFT_SPLITBF16) && (flags & LJSDE_FP64))
+        return fail(LJSDE_EINVAL, "LJSDE_DFT_SPLITBF16 applies to FP32 plans only");
+    if (!(window == 32 || window == 16))
+        return fail(LJSDE_EUNSUPPORTED, "no kernel for window %d (have 16, 32)", window);
+    if (!(block == 4 || block == 8))
+        return fail(LJSDE_EUNSUPPORTED, "no kernel for block %d (have 4, 8)", block);
+    if (iters > 32767) return fail(LJSDE_EUNSUPPORTED, "iters %d above 32767", iters);
+    auto p = std::make_unique<Plan>();
+    p->pattern.assign(pattern, pattern + (size_t)pat_rows * pat_cols);
+    p->pr = pat_rows;
+    p->pc = pat_cols;
+    p->W = window;
+    p->B = block;
+    p->Ws = window / 2;
+    p->iters = iters;
+    p->rho = rho;
+    p->gamma = gamma;
+    p->flags = flags;
+    p->lay = make_layout(p->W, p->Ws);
+    build_constants(*p);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_plans.push_back(std::move(p));
+    ok();
+    return (int)g_plans.size() - 1;
+}
+
+int ljsde_set_energy_floor(int pattern_id, double tau) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *p = nullptr;
+    int st = get_plan(pattern_id, &p);
+    if (st) return st;
+    if (!(tau >= 0.0 && tau < 1.0)) return fail(LJSDE_EINVAL, "tau %g must be in [0, 1)", tau);
+    p->tau = tau;
+    return ok();
+}
+
+static int reconstruct_impl(const void *y, int Ms, int Ns, int id, void *out, int16_t *sel, void *stream) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *p = nullptr;
+    int st = get_plan(id, &p);
+    if (st) return st;
+    if (!y || !out) return fail(LJSDE_EINVAL, "null device pointer");
+    SizeSet *s = nullptr;
+    st = get_size(*p, Ms, Ns, &s);
+    if (st) return st;
+    st = ensure_device(*p, *s);
+    if (st) return st;
+    KParams k = make_params(*p);
+    KJob j = make_job(*s, y, out, sel, 0);
+    int e = 0;
+    if (p->fp64()) {
+        e = launch_plain_f64(k, j, p->Ws, stream);
+    } else if (sel) {
+        e = launch_plain_f32(k, j, p->Ws, stream);
+    } else {
+        ljsde_job job{y, Ms, Ns, id, out};
+        return run_batch(&job, 1, stream);
+    }
+    if (e) return fail(LJSDE_EHIP, "kernel launch: %s", hipGetErrorString((hipError_t)e));
+    return ok();
+}
+
+int ljsde_reconstruct(const void *measurements, int sensor_rows, int sensor_cols, int pattern_id, void *out,
+                      void *stream) {
+    return reconstruct_impl(measurements, sensor_rows, sensor_cols, pattern_id, out, nullptr, stream);
+}
+
+int ljsde_reconstruct_diag(const void *measurements, int sensor_rows, int sensor_cols, int pattern_id,
+                           void *out, int16_t *selections, void *stream) {
+    if (!selections) return fail(LJSDE_EINVAL, "selections is null");
+    return reconstruct_impl(measurements, sensor_rows, sensor_cols, pattern_id, out, selections, stream);
+}
+
+int ljsde_reconstruct_batch(const ljsde_job *jobs, int n_jobs, void *stream) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return run_batch(jobs, n_jobs, stream);
+}
+
+int ljsde_autotune(const ljsde_job *jobs, int n_jobs, void *stream) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    BatchState *b = nullptr;
+    int st = prepare_batch(jobs, n_jobs, stream, &b);
+    if (st) return st;
+    const TuneChoice cands[] = {{1, 1}, {1, 2}, {1, 4}, {1, 8}, {2, 2}, {2, 4}, {4, 2}, {4, 4}};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    TuneChoice best = b->choice;
+    int best_grid = b->grid;
+    for (const TuneChoice &c : cands) {
+        int grid = 0;
+        st = grid_for(b->ws, c, &grid);
+        if (st) break;
+        st = launch_batch_eager(*b, c, grid, stream);  // warm-up
+        if (st) break;
+        float total = 0;
+        const int reps = 3;
+        (void)hipEventRecord(e0, (hipStream_t)stream);
+        for (int r = 0; r < reps && !st; ++r) st = launch_batch_eager(*b, c, grid, stream);
+        (void)hipEventRecord(e1, (hipStream_t)stream);
+        if (st) break;
+        hipError_t e = hipEventSynchronize(e1);
+        if (e != hipSuccess) {
+            st = fail(LJSDE_EHIP, "autotune: %s", hipGetErrorString(e));
+            break;
+        }
+        (void)hipEventElapsedTime(&total, e0, e1);
+        if (total / reps < best_ms) {
+            best_ms = total / reps;
+            best = c;
+            best_grid = grid;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    b->choice = best;
+    b->grid = best_grid;
+    Plan *p0 = nullptr;
+    get_plan(jobs[0].pattern_id, &p0);
+    int n_classes = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        Plan *p = nullptr;
+        get_plan(jobs[i].pattern_id, &p);
+        SizeSet *s = nullptr;
+        get_size(*p, jobs[i].sensor_rows, jobs[i].sensor_cols, &s);
+        n_classes = std::max(n_classes, s->n_classes());
+    }
+    g_tuned[tune_key(*p0, b->total, n_classes)] = best;
+    save_tune_cache();
+    st = capture_graph(*b);
+    if (st) return st;
+    return ok();
+}
+
+int ljsde_synchronize(void *stream) {
+    int dev = 0;
+    int st = current_device(&dev);
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    HIP_TRY(hipGetLastError());
+    return ok();
+}
+
+int ljsde_release(int pattern_id) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *p = nullptr;
+    int st = get_plan(pattern_id, &p);
+    if (st) return st;
+    // batches that reference this plan hold device pointers into its tables
+    for (auto it = g_batches.begin(); it != g_batches.end();) {
+        bool uses = false;
+        std::string k = it->first;
+        std::string pref = std::to_string(pattern_id) + ":";
+        if (k.compare(0, pref.size(), pref) == 0 || k.find(";" + pref) != std::string::npos) uses = true;
+        it = uses ? g_batches.erase(it) : std::next(it);
+    }
+    if (p->d_consts) (void)hipDeviceSynchronize();
+    for (auto &kv : p->sizes) {
+        SizeSet &s = *kv.second;
+        if (s.d_tables) (void)hipFree(s.d_tables);
+        if (s.d_rowcls) (void)hipFree(s.d_rowcls);
+        if (s.d_colcls) (void)hipFree(s.d_colcls);
+    }
+    if (p->d_consts) (void)hipFree(p->d_consts);
+    g_plans[pattern_id].reset();
+    return ok();
+}
+
+int ljsde_class_count(int pattern_id, int sensor_rows, int sensor_cols, int32_t *class_of_window) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *p = nullptr;
+    int st = get_plan(pattern_id, &p);
+    if (st) return st;
+    SizeSet *s = nullptr;
+    st = get_size(*p, sensor_rows, sensor_cols, &s);
+    if (st) return st;
+    if (class_of_window) {
+        const int nck = (int)s->colkeys.size();
+        for (int bi = 0; bi < s->nbi; ++bi)
+            for (int bj = 0; bj < s->nbj; ++bj)
+                class_of_window[(size_t)bi * s->nbj + bj] = s->rowcls[bi] * nck + s->colcls[bj];
+    }
+    ok();
+    return s->n_classes();
+}
+
+int ljsde_class_tables(int pattern_id, int sensor_rows, int sensor_cols, int class_index, double *S, double *D,
+                       int8_t *codes) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *p = nullptr;
+    int st = get_plan(pattern_id, &p);
+    if (st) return st;
+    SizeSet *s = nullptr;
+    st = get_size(*p, sensor_rows, sensor_cols, &s);
+    if (st) return st;
+    if (class_index < 0 || class_index >= s->n_classes())
+        return fail(LJSDE_EINVAL, "class %d out of range [0, %d)", class_index, s->n_classes());
+    build_host_tables(*p, *s);
+    const unsigned char *blk = s->blob.data() + (size_t)class_index * p->lay.stride;
+    if (S) memcpy(S, blk + p->lay.offS, sizeof(double) * p->Ws * p->Ws * 8);
+    if (D) memcpy(D, s->D.data() + (size_t)class_index * p->W * p->W, sizeof(double) * p->W * p->W);
+    if (codes) memcpy(codes, blk + p->lay.offCodes, p->Ws * p->Ws);
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// Shared host/device declarations of the RL-JSDE library (not part of the ABI).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ljsde {
+
+// Class-independent constants, FP64, on the device.
+struct DevConsts {
+    const double *w;    // [Ws*Ws] spatial weights w_m = rho^d_m (eq. (8))
+    const double *ew;   // [W][2]  exp(+i 2 pi k / W), k < W
+    const double *dft;  // [Ws][2] exp(-i 2 pi k / Ws), k < Ws
+};
+
+// Byte offsets inside one class block of the device table.
+struct ClassLayout {
+    int offS;      // double [Ws*Ws][4][2]  S_o(k, l)
+    int offQD64;   // double [W*W]          q / D   (0 where D <= 0)
+    int offInvD;   // double [W*W]          1 / D   (0 where D <= 0)
+    int offQD32;   // float  [W*W]          q / D
+    int offCodes;  // int8   [Ws*Ws]        code, -1 outside the image
+    int stride;    // bytes per class (multiple of 256)
+};
+
+struct KParams {
+    int W;         // model window side
+    int B;         // target block side
+    int off;       // (W - B) / 2
+    int iters;     // nu_max
+    double gamma;  // gamma_odc
+    double ecoef;  // 2 gamma - gamma^2
+    double tau;    // energy floor (0 = off)
+    DevConsts c;
+    ClassLayout lay;
+};
+
+// One image as seen by the kernels.
+struct KJob {
+    const void *y;                 // sensor image, Ms x Ns
+    void *out;                     // 2Ms x 2Ns
+    const unsigned char *tables;   // class blocks
+    const int *rowcls;             // [nbi] row key index
+    const int *colcls;             // [nbj] column key index
+    int16_t *sel;                  // [nwin][iters] or null
+    int Ms, Ns, nbi, nbj, ncolk;
+    long long win_begin;           // first global window index of this job
+};
+
+// Launch wrappers (ljsde_kernels.hip). Return a hipError_t value.
+int launch_plain_f64(const KParams &p, const KJob &job, int ws, void *stream);
+int launch_plain_f32(const KParams &p, const KJob &job, int ws, void *stream);
+int launch_reset_counter(unsigned int *counter, void *stream);
+int launch_persistent_f32(const KParams &p, const KJob *d_jobs, int njobs, long long total_windows,
+                          unsigned int *counter, int ws, int waves_per_block, int chunk,
+                          int grid, void *stream);
+int persistent_blocks_per_cu(int ws, int waves_per_block, int *blocks);
+size_t lds_bytes_per_wave(int ws, bool fp64);
+
+}  // namespace ljsde

@@ -1,0 +1,403 @@
+// HIP kernels of the RL-JSDE hot path for gfx950 (CDNA4, wave64).
+//
+// One wavefront models one window. The loop state is the factorised
+// projected residual: for each opaque-quadrant orientation o the (W/2)-point
+// 2-D DFT of the weighted residual restricted to the sensor pixels of that
+// orientation,
+//     P_o(k, l) = sum_{m: o_m = o} w_m r_m exp(-2 pi i (i' k + j' l) / Ws),
+// from which the projected residual of eq. (12) follows for every frequency
+// (sigma, rho) = (k + Ws a, l + Ws b) as
+//     R(sigma, rho) = sum_o conj(H_o(sigma, rho)) P_o(k, l),
+// with H_o the response of the L-shaped pixel of orientation o to the basis
+// function (the box response of the 2x2 footprint minus the opaque quadrant).
+// Selecting (u, v) by eq. (11) and taking the step of eqs. (15)-(16) changes
+// every P_o by the orientation's weighted-mask spectrum S_o shifted by (u, v)
+// (eq. (17) in factorised form):
+//     P_o(k, l) -= gamma delta H_o(u, v) S_o(k - u, l - v).
+// S_o, q / D and 1 / D come from the per-class FP64 tables.
+//
+// Lane layout (Ws = 16): lane L owns the (k, l) positions
+// k = 4 (L / 16) + t (t < 4), l = L % 16, i.e. 16 frequencies. The 4x4
+// frequencies of one position are formed from its four P_o by a twiddle step
+// and a 2x2 Walsh-Hadamard step. S_o lives in LDS; the state, the per-lane
+// q / D and the twiddles live in VGPRs.
+#include <hip/hip_runtime.h>
+
+#include "ljsde_internal.h"
+
+namespace ljsde {
+
+template <typename T>
+struct C2 {
+    T re, im;
+};
+
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T load_qd(const double *qd64, const float *qd32, int i);
+template <>
+__device__ __forceinline__ double load_qd<double>(const double *qd64, const float *, int i) {
+    return qd64[i];
+}
+template <>
+__device__ __forceinline__ float load_qd<float>(const double *, const float *qd32, int i) {
+    return qd32[i];
+}
+
+template <typename T, int WS>
+struct WinLds {
+    static constexpr int NPOS = WS * WS;
+    static constexpr size_t bytes = (size_t)NPOS * 8 * sizeof(T) + NPOS * sizeof(T) + NPOS;
+};
+
+template <typename T, int WS>
+__device__ __forceinline__ void process_window(const KParams &p, const KJob &j, int bi, int bj,
+                                               long long win_local, char *lds) {
+    constexpr int W = 2 * WS;
+    constexpr int QPL = WS * WS / 64;
+    constexpr int NPOS = WS * WS;
+    const int lane = threadIdx.x & 63;
+    const int lam = lane % WS;
+    const int kap0 = (lane / WS) * QPL;
+
+    const int cls = j.rowcls[bi] * j.ncolk + j.colcls[bj];
+    const unsigned char *tb = j.tables + (size_t)cls * p.lay.stride;
+    const double *S64 = (const double *)(tb + p.lay.offS);
+    const double *qD64 = (const double *)(tb + p.lay.offQD64);
+    const double *invD = (const double *)(tb + p.lay.offInvD);
+    const float *qD32 = (const float *)(tb + p.lay.offQD32);
+    const signed char *codes = (const signed char *)(tb + p.lay.offCodes);
+
+    T *ldsS = (T *)lds;                 // stage buffer, then S_o: [pos][o][re, im]
+    T *ldsX = ldsS + NPOS * 8;          // weighted measurements w_m y_m
+    signed char *ldsC = (signed char *)(ldsX + NPOS);
+
+    wave_lds_fence();  // previous window of this wave is done with the LDS
+
+    // ---- gather the window's sensor tile (absent pixels -> 0) -------------
+    const int rs = (p.B * bi - p.off) / 2;
+    const int cs = (p.B * bj - p.off) / 2;
+    const T *Y = (const T *)j.y;
+    double e0 = 0.0;
+    for (int m = lane; m < NPOS; m += 64) {
+        const int ip = m / WS, jp = m % WS;
+        const int gi = rs + ip, gj = cs + jp;
+        signed char code = codes[m];
+        T x = T(0);
+        if (code >= 0 && gi >= 0 && gi < j.Ms && gj >= 0 && gj < j.Ns) {
+            const double yv = (double)Y[(size_t)gi * j.Ns + gj];
+            const double wy = p.c.w[m] * yv;
+            x = (T)wy;
+            e0 += wy * yv;
+        } else {
+            code = -1;
+        }
+        ldsX[m] = x;
+        ldsC[m] = code;
+    }
+    e0 = wave_sum(e0);  // weighted residual energy of eq. (8) at iteration 0
+    wave_lds_fence();
+
+    // ---- orientation-masked weighted DFT, rows then columns ---------------
+#pragma unroll 1
+    for (int s = 0; s < QPL; ++s) {
+        const int ip = kap0 + s;
+        C2<T> acc[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) acc[o] = {T(0), T(0)};
+#pragma unroll 2
+        for (int jp = 0; jp < WS; ++jp) {
+            const T x = ldsX[ip * WS + jp];
+            const int c = ldsC[ip * WS + jp];
+            const int k = (jp * lam) & (WS - 1);
+            const T twr = (T)p.c.dft[2 * k], twi = (T)p.c.dft[2 * k + 1];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                const T xo = (c == o) ? x : T(0);
+                acc[o].re += xo * twr;
+                acc[o].im += xo * twi;
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            ldsS[((ip * WS + lam) * 4 + o) * 2] = acc[o].re;
+            ldsS[((ip * WS + lam) * 4 + o) * 2 + 1] = acc[o].im;
+        }
+    }
+    wave_lds_fence();
+
+    C2<T> P[QPL][4];
+#pragma unroll
+    for (int t = 0; t < QPL; ++t) {
+        const int kap = kap0 + t;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) P[t][o] = {T(0), T(0)};
+#pragma unroll 2
+        for (int ip = 0; ip < WS; ++ip) {
+            const int k = (ip * kap) & (WS - 1);
+            const T twr = (T)p.c.dft[2 * k], twi = (T)p.c.dft[2 * k + 1];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                const T ar = ldsS[((ip * WS + lam) * 4 + o) * 2];
+                const T ai = ldsS[((ip * WS + lam) * 4 + o) * 2 + 1];
+                P[t][o].re += ar * twr - ai * twi;
+                P[t][o].im += ar * twi + ai * twr;
+            }
+        }
+    }
+    wave_lds_fence();
+
+    // ---- class spectra S_o into LDS (FP64 table -> working precision) ------
+    for (int e = lane; e < NPOS * 8; e += 64) ldsS[e] = (T)S64[e];
+
+    // ---- per-lane constants -------------------------------------------------
+    T qd[QPL][4];
+    C2<T> tk[QPL], tkl[QPL];
+#pragma unroll
+    for (int t = 0; t < QPL; ++t) {
+        const int kap = kap0 + t;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                qd[t][a * 2 + b] = load_qd<T>(qD64, qD32, (kap + WS * a) * W + lam + WS * b);
+        tk[t] = {(T)p.c.ew[2 * kap], (T)-p.c.ew[2 * kap + 1]};
+        tkl[t] = {(T)p.c.ew[2 * (kap + lam)], (T)-p.c.ew[2 * (kap + lam) + 1]};
+    }
+    const C2<T> tl = {(T)p.c.ew[2 * lam], (T)-p.c.ew[2 * lam + 1]};
+    wave_lds_fence();
+
+    const int BB = p.B * p.B;
+    const int oi = lane / p.B, oj = lane % p.B;
+    double outacc = 0.0;
+    double E = e0;
+    C2<T> g4[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) g4[o] = {T(0), T(0)};
+    int u = 0, v = 0;
+    int nu_done = 0;
+
+#pragma unroll 1
+    for (int nu = 0; nu < p.iters; ++nu) {
+        T best0 = T(-1), best1 = T(-1);
+        int code0 = 0, code1 = 0;
+#pragma unroll
+        for (int t = 0; t < QPL; ++t) {
+            const int kap = kap0 + t;
+            if (nu > 0) {
+                // subtract the shifted weighted-mask spectra of the last pick
+                const int pos = ((kap - u) & (WS - 1)) * WS + ((lam - v) & (WS - 1));
+                const T *s = ldsS + pos * 8;
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    const T sr = s[2 * o], si = s[2 * o + 1];
+                    P[t][o].re -= g4[o].re * sr - g4[o].im * si;
+                    P[t][o].im -= g4[o].re * si + g4[o].im * sr;
+                }
+            }
+            // project: R(a, b) = sum_q (-1)^(qa a + qb b) e^{-i theta (qa k + qb l)} (sum P - P_q)
+            const C2<T> sp = {P[t][0].re + P[t][1].re + P[t][2].re + P[t][3].re,
+                              P[t][0].im + P[t][1].im + P[t][2].im + P[t][3].im};
+            const C2<T> q0 = {sp.re - P[t][0].re, sp.im - P[t][0].im};
+            const C2<T> q1 = {sp.re - P[t][1].re, sp.im - P[t][1].im};
+            const C2<T> q2 = {sp.re - P[t][2].re, sp.im - P[t][2].im};
+            const C2<T> q3 = {sp.re - P[t][3].re, sp.im - P[t][3].im};
+            const C2<T> u1 = {tl.re * q1.re - tl.im * q1.im, tl.re * q1.im + tl.im * q1.re};
+            const C2<T> u2 = {tk[t].re * q2.re - tk[t].im * q2.im, tk[t].re * q2.im + tk[t].im * q2.re};
+            const C2<T> u3 = {tkl[t].re * q3.re - tkl[t].im * q3.im,
+                              tkl[t].re * q3.im + tkl[t].im * q3.re};
+            const C2<T> s1 = {q0.re + u3.re, q0.im + u3.im}, d1 = {q0.re - u3.re, q0.im - u3.im};
+            const C2<T> s2 = {u1.re + u2.re, u1.im + u2.im}, d2 = {u1.re - u2.re, u1.im - u2.im};
+            const C2<T> r00 = {s1.re + s2.re, s1.im + s2.im};
+            const C2<T> r01 = {d1.re - d2.re, d1.im - d2.im};
+            const C2<T> r10 = {d1.re + d2.re, d1.im + d2.im};
+            const C2<T> r11 = {s1.re - s2.re, s1.im - s2.im};
+            // eq. (11) metric q |R|^2 / D; first maximum in sigma * W + rho order
+            const T m00 = (r00.re * r00.re + r00.im * r00.im) * qd[t][0];
+            const T m01 = (r01.re * r01.re + r01.im * r01.im) * qd[t][1];
+            const T m10 = (r10.re * r10.re + r10.im * r10.im) * qd[t][2];
+            const T m11 = (r11.re * r11.re + r11.im * r11.im) * qd[t][3];
+            if (m00 > best0) { best0 = m00; code0 = 2 * t; }
+            if (m01 > best0) { best0 = m01; code0 = 2 * t + 1; }
+            if (m10 > best1) { best1 = m10; code1 = 2 * t; }
+            if (m11 > best1) { best1 = m11; code1 = 2 * t + 1; }
+        }
+        T best;
+        int code, a;
+        if (best1 > best0) { best = best1; code = code1; a = 1; }
+        else { best = best0; code = code0; a = 0; }
+        int idx = (kap0 + (code >> 1) + WS * a) * W + lam + WS * (code & 1);
+        for (int o = 32; o > 0; o >>= 1) {
+            const T ob = __shfl_xor(best, o);
+            const int oid = __shfl_xor(idx, o);
+            if (ob > best || (ob == best && oid < idx)) { best = ob; idx = oid; }
+        }
+        idx = __builtin_amdgcn_readfirstlane(idx);
+        u = idx / W;
+        v = idx % W;
+
+        // L-pixel responses of the selected basis function, FP64
+        const double eur = p.c.ew[2 * u], eui = p.c.ew[2 * u + 1];
+        const double evr = p.c.ew[2 * v], evi = p.c.ew[2 * v + 1];
+        const int uv = (u + v) & (W - 1);
+        const double euvr = p.c.ew[2 * uv], euvi = p.c.ew[2 * uv + 1];
+        const double hbr = (1.0 + eur) * (1.0 + evr) - eui * evi;
+        const double hbi = (1.0 + eur) * evi + eui * (1.0 + evr);
+        double Hr[4] = {hbr - 1.0, hbr - evr, hbr - eur, hbr - euvr};
+        double Hi[4] = {hbi, hbi - evi, hbi - eui, hbi - euvi};
+
+        // R_uv in FP64 from the owner lane's state
+        const int ku = u & (WS - 1), lv = v & (WS - 1);
+        const int tu = ku % QPL;
+        const int owner = (ku / QPL) * WS + lv;
+        C2<T> Pu[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) Pu[o] = P[0][o];
+#pragma unroll
+        for (int t = 1; t < QPL; ++t)
+            if (tu == t) {
+#pragma unroll
+                for (int o = 0; o < 4; ++o) Pu[o] = P[t][o];
+            }
+        double rr = 0.0, ri = 0.0;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const double pr = (double)Pu[o].re, pi = (double)Pu[o].im;
+            rr += Hr[o] * pr + Hi[o] * pi;
+            ri += Hr[o] * pi - Hi[o] * pr;
+        }
+        rr = __shfl(rr, owner);
+        ri = __shfl(ri, owner);
+
+        // eqs. (15)-(16): delta = R_uv / D_uv, step gamma * delta; energy in FP64
+        const double id = invD[idx];
+        const double gr = p.gamma * rr * id, gi = p.gamma * ri * id;
+        E -= p.ecoef * (rr * rr + ri * ri) * id;
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+            g4[o] = {(T)(gr * Hr[o] - gi * Hi[o]), (T)(gr * Hi[o] + gi * Hr[o])};
+
+        // eq. (18) restricted to the central block, accumulated pick by pick
+        if (lane < BB) {
+            const int ph = ((p.off + oi) * u + (p.off + oj) * v) & (W - 1);
+            outacc += gr * p.c.ew[2 * ph] - gi * p.c.ew[2 * ph + 1];
+        }
+        if (j.sel != nullptr && lane == 0) j.sel[win_local * p.iters + nu] = (int16_t)idx;
+        nu_done = nu + 1;
+        if (p.tau > 0.0 && E <= p.tau * e0) break;
+    }
+    if (j.sel != nullptr)
+        for (int nu = nu_done + lane; nu < p.iters; nu += 64) j.sel[win_local * p.iters + nu] = -1;
+
+    if (lane < BB) {
+        T *O = (T *)j.out;
+        const size_t row = (size_t)(p.B * bi + oi);
+        O[row * (size_t)(2 * j.Ns) + (size_t)(p.B * bj + oj)] = (T)outacc;
+    }
+}
+
+template <typename T, int WS>
+__global__ __launch_bounds__(64) void plain_kernel(KParams p, KJob j) {
+    extern __shared__ char lds[];
+    const long long w = blockIdx.x;
+    const long long nwin = (long long)j.nbi * j.nbj;
+    if (w >= nwin) return;
+    process_window<T, WS>(p, j, (int)(w / j.nbj), (int)(w % j.nbj), w, lds);
+}
+
+__global__ void reset_counter_kernel(unsigned int *counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+}
+
+template <typename T, int WS>
+__global__ __launch_bounds__(256) void persistent_kernel(KParams p, const KJob *__restrict__ jobs,
+                                                         int njobs, long long total,
+                                                         unsigned int *counter, int chunk) {
+    extern __shared__ char lds[];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    char *mylds = lds + (size_t)wave * WinLds<T, WS>::bytes;
+    for (;;) {
+        unsigned int start = 0;
+        if (lane == 0) start = atomicAdd(counter, (unsigned int)chunk);
+        start = __shfl(start, 0);
+        start = __builtin_amdgcn_readfirstlane(start);
+        if ((long long)start >= total) break;
+        const long long end = min((long long)start + chunk, total);
+        for (long long gw = start; gw < end; ++gw) {
+            int lo = 0, hi = njobs - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (jobs[mid].win_begin <= gw) lo = mid;
+                else hi = mid - 1;
+            }
+            const KJob j = jobs[lo];
+            const long long lw = gw - j.win_begin;
+            process_window<T, WS>(p, j, (int)(lw / j.nbj), (int)(lw % j.nbj), lw, mylds);
+        }
+    }
+}
+
+size_t lds_bytes_per_wave(int ws, bool fp64) {
+    if (ws == 16) return fp64 ? WinLds<double, 16>::bytes : WinLds<float, 16>::bytes;
+    return fp64 ? WinLds<double, 8>::bytes : WinLds<float, 8>::bytes;
+}
+
+template <typename T, int WS>
+static int launch_plain_t(const KParams &p, const KJob &job, void *stream) {
+    const long long nwin = (long long)job.nbi * job.nbj;
+    if (nwin <= 0) return 0;
+    const size_t lds = WinLds<T, WS>::bytes;
+    plain_kernel<T, WS><<<dim3((unsigned)nwin), dim3(64), lds, (hipStream_t)stream>>>(p, job);
+    return (int)hipGetLastError();
+}
+
+int launch_plain_f64(const KParams &p, const KJob &job, int ws, void *stream) {
+    return ws == 16 ? launch_plain_t<double, 16>(p, job, stream) : launch_plain_t<double, 8>(p, job, stream);
+}
+
+int launch_plain_f32(const KParams &p, const KJob &job, int ws, void *stream) {
+    return ws == 16 ? launch_plain_t<float, 16>(p, job, stream) : launch_plain_t<float, 8>(p, job, stream);
+}
+
+int launch_reset_counter(unsigned int *counter, void *stream) {
+    reset_counter_kernel<<<dim3(1), dim3(64), 0, (hipStream_t)stream>>>(counter);
+    return (int)hipGetLastError();
+}
+
+int launch_persistent_f32(const KParams &p, const KJob *d_jobs, int njobs, long long total_windows,
+                          unsigned int *counter, int ws, int waves_per_block, int chunk, int grid,
+                          void *stream) {
+    const size_t lds = (size_t)waves_per_block * lds_bytes_per_wave(ws, false);
+    if (ws == 16)
+        persistent_kernel<float, 16><<<dim3(grid), dim3(64 * waves_per_block), lds, (hipStream_t)stream>>>(
+            p, d_jobs, njobs, total_windows, counter, chunk);
+    else
+        persistent_kernel<float, 8><<<dim3(grid), dim3(64 * waves_per_block), lds, (hipStream_t)stream>>>(
+            p, d_jobs, njobs, total_windows, counter, chunk);
+    return (int)hipGetLastError();
+}
+
+int persistent_blocks_per_cu(int ws, int waves_per_block, int *blocks) {
+    const size_t lds = (size_t)waves_per_block * lds_bytes_per_wave(ws, false);
+    hipError_t e;
+    if (ws == 16)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, persistent_kernel<float, 16>,
+                                                         64 * waves_per_block, lds);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, persistent_kernel<float, 8>,
+                                                         64 * waves_per_block, lds);
+    return (int)e;
+}
+
+}  // namespace ljsde

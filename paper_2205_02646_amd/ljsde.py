@@ -1,0 +1,215 @@
+"""Python binding of the RL-JSDE C ABI (``include/ljsde.h``).
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+kernels of ``libljsde.so``. PyTorch provides device memory and streams.
+Loading fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libljsde.so")
+
+OK = 0
+EINVAL = -1
+EUNSUPPORTED = -2
+ENOMEM = -3
+EHIP = -4
+EBADID = -5
+
+FP64 = 1
+FP32 = 2
+DFT_SPLITBF16 = 4
+Q_ONES = 8
+
+_NAMES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOMEM: "ENOMEM", EHIP: "EHIP", EBADID: "EBADID"}
+
+
+class LjsdeError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+class Job(ctypes.Structure):
+    _fields_ = [
+        ("measurements", ctypes.c_void_p),
+        ("sensor_rows", ctypes.c_int),
+        ("sensor_cols", ctypes.c_int),
+        ("pattern_id", ctypes.c_int),
+        ("out", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2205_02646_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    i, d, u, vp = ctypes.c_int, ctypes.c_double, ctypes.c_uint, ctypes.c_void_p
+    L.ljsde_plan.argtypes = [ctypes.POINTER(ctypes.c_uint8), i, i, i, i, i, d, d, u]
+    L.ljsde_set_energy_floor.argtypes = [i, d]
+    L.ljsde_reconstruct.argtypes = [vp, i, i, i, vp, vp]
+    L.ljsde_reconstruct_diag.argtypes = [vp, i, i, i, vp, vp, vp]
+    L.ljsde_reconstruct_batch.argtypes = [ctypes.POINTER(Job), i, vp]
+    L.ljsde_autotune.argtypes = [ctypes.POINTER(Job), i, vp]
+    L.ljsde_synchronize.argtypes = [vp]
+    L.ljsde_release.argtypes = [i]
+    L.ljsde_last_error.restype = ctypes.c_char_p
+    L.ljsde_class_count.argtypes = [i, i, i, vp]
+    L.ljsde_class_tables.argtypes = [i, i, i, i, vp, vp, vp]
+    L.ljsde_plan_info.argtypes = [i, vp, vp, vp, vp]
+    for name in ("ljsde_plan", "ljsde_set_energy_floor", "ljsde_reconstruct", "ljsde_reconstruct_diag",
+                 "ljsde_reconstruct_batch", "ljsde_autotune", "ljsde_synchronize", "ljsde_release",
+                 "ljsde_class_count", "ljsde_class_tables", "ljsde_plan_info", "ljsde_version"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        raise LjsdeError(status, lib().ljsde_last_error().decode())
+    return status
+
+
+def last_error() -> str:
+    return lib().ljsde_last_error().decode()
+
+
+def version() -> int:
+    return lib().ljsde_version()
+
+
+def plan(pattern, window: int = 32, block: int = 4, iters: int = 100, rho: float = 0.7,
+         gamma: float = 0.5, fp64: bool = False, splitbf16: bool = False, q_ones: bool = False) -> int:
+    """Register a plan for an opaque-quadrant pattern tile; returns its id."""
+    pat = np.ascontiguousarray(np.asarray(pattern, dtype=np.uint8))
+    if pat.ndim != 2:
+        raise ValueError("pattern must be 2-D")
+    flags = (FP64 if fp64 else FP32) | (DFT_SPLITBF16 if splitbf16 else 0) | (Q_ONES if q_ones else 0)
+    return _check(lib().ljsde_plan(pat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), pat.shape[0],
+                                   pat.shape[1], window, block, iters, rho, gamma, flags))
+
+
+def set_energy_floor(pid: int, tau: float) -> None:
+    _check(lib().ljsde_set_energy_floor(pid, tau))
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _as_input(y, dtype):
+    import torch
+    if not (isinstance(y, torch.Tensor) and y.is_cuda):
+        raise TypeError("measurements must be a CUDA (HIP) tensor")
+    if y.dtype != dtype or y.dim() != 2 or not y.is_contiguous():
+        raise TypeError(f"measurements must be a contiguous 2-D {dtype} tensor")
+    return y
+
+
+def reconstruct(y, pid: int, out=None, fp64: Optional[bool] = None, stream=None, selections=None):
+    """Reconstruct one image. ``y`` is a contiguous 2-D device tensor (float32
+    for FP32 plans, float64 for FP64 plans); returns ``out`` (2R x 2C)."""
+    import torch
+    if fp64 is None:
+        fp64 = y.dtype == torch.float64
+    dtype = torch.float64 if fp64 else torch.float32
+    _as_input(y, dtype)
+    R, C = y.shape
+    if out is None:
+        out = torch.empty((2 * R, 2 * C), dtype=dtype, device=y.device)
+    elif out.shape != (2 * R, 2 * C) or out.dtype != dtype or not out.is_contiguous():
+        raise TypeError("out has the wrong shape, dtype or layout")
+    if selections is None:
+        _check(lib().ljsde_reconstruct(y.data_ptr(), R, C, pid, out.data_ptr(), _stream(stream)))
+    else:
+        _check(lib().ljsde_reconstruct_diag(y.data_ptr(), R, C, pid, out.data_ptr(), selections.data_ptr(),
+                                            _stream(stream)))
+    return out
+
+
+def reconstruct_diag(y, pid: int, out=None, stream=None):
+    """As ``reconstruct``; also returns the int16 selection sequences
+    [n_windows, iters] (sigma * W + rho per iteration, -1 after a stop)."""
+    import torch
+    info = plan_info(pid)
+    R, C = y.shape
+    n_win = (2 * R // info["block"]) * (2 * C // info["block"])
+    sel = torch.empty((n_win, info["iters"]), dtype=torch.int16, device=y.device)
+    out = reconstruct(y, pid, out=out, stream=stream, selections=sel)
+    return out, sel
+
+
+def plan_info(pid: int) -> dict:
+    w, b, it, fl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_uint()
+    _check(lib().ljsde_plan_info(pid, ctypes.byref(w), ctypes.byref(b), ctypes.byref(it), ctypes.byref(fl)))
+    return dict(window=w.value, block=b.value, iters=it.value, flags=fl.value)
+
+
+def _jobs(items: Sequence) -> ctypes.Array:
+    arr = (Job * len(items))()
+    for k, (y, pid, out) in enumerate(items):
+        arr[k] = Job(y.data_ptr(), y.shape[0], y.shape[1], pid, out.data_ptr())
+    return arr
+
+
+def reconstruct_batch(items: Iterable, stream=None) -> None:
+    """``items``: sequence of (y, plan_id, out) with float32 device tensors."""
+    import torch
+    items = list(items)
+    for y, _, out in items:
+        _as_input(y, torch.float32)
+        if out.dtype != torch.float32 or out.shape != (2 * y.shape[0], 2 * y.shape[1]) or not out.is_contiguous():
+            raise TypeError("out has the wrong shape, dtype or layout")
+    arr = _jobs(items)
+    _check(lib().ljsde_reconstruct_batch(arr, len(items), _stream(stream)))
+
+
+def autotune(items: Iterable, stream=None) -> None:
+    items = list(items)
+    arr = _jobs(items)
+    _check(lib().ljsde_autotune(arr, len(items), _stream(stream)))
+
+
+def synchronize(stream=None) -> None:
+    _check(lib().ljsde_synchronize(_stream(stream)))
+
+
+def release(pid: int) -> None:
+    _check(lib().ljsde_release(pid))
+
+
+def class_map(pid: int, sensor_rows: int, sensor_cols: int):
+    """(class count, int32 class index per window in row-major block order)."""
+    B = plan_info(pid)["block"]
+    n_win = (2 * sensor_rows // B) * (2 * sensor_cols // B) if sensor_rows > 0 and sensor_cols > 0 else 0
+    buf = np.empty(max(n_win, 1), dtype=np.int32)
+    n = _check(lib().ljsde_class_count(pid, sensor_rows, sensor_cols, buf.ctypes.data))
+    return n, buf[:n_win]
+
+
+def class_tables(pid: int, sensor_rows: int, sensor_cols: int, cls: int, window: int):
+    """FP64 tables of one class: (S [Ws*Ws, 4] complex, D [W*W], codes [Ws, Ws])."""
+    ws = window // 2
+    S = np.empty((ws * ws, 4, 2), dtype=np.float64)
+    D = np.empty(window * window, dtype=np.float64)
+    codes = np.empty(ws * ws, dtype=np.int8)
+    _check(lib().ljsde_class_tables(pid, sensor_rows, sensor_cols, cls, S.ctypes.data, D.ctypes.data,
+                                    codes.ctypes.data))
+    return S[..., 0] + 1j * S[..., 1], D, codes.reshape(ws, ws)

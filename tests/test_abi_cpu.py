@@ -1,0 +1,222 @@
+"""Host-side tests of the C ABI (no GPU needed): exported symbols, argument
+validation, class enumeration and the FP64 per-class tables, checked against
+the oracle's dense B, C, D of Sec. IV."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import ljsde_oracle as O
+from paper_2205_02646_amd import ljsde
+from synth import make_case, random_pattern
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "ljsde.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ljsde_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = _header_functions()
+    assert len(names) >= 12
+    lib = ctypes.CDLL(ljsde.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert ljsde.version() >= 10000
+
+
+def _no_gpu():
+    import torch
+    return torch.cuda.device_count() == 0
+
+
+TILE = random_pattern(4, 4, seed=0)
+
+
+@pytest.mark.parametrize("kwargs,code", [
+    (dict(window=30), ljsde.EINVAL),            # (W - B) not divisible by 4
+    (dict(window=32, block=6), ljsde.EINVAL),
+    (dict(window=33), ljsde.EINVAL),
+    (dict(block=0), ljsde.EINVAL),
+    (dict(iters=0), ljsde.EINVAL),
+    (dict(rho=0.0), ljsde.EINVAL),
+    (dict(rho=1.5), ljsde.EINVAL),
+    (dict(gamma=0.0), ljsde.EINVAL),
+    (dict(gamma=2.0), ljsde.EINVAL),
+    (dict(window=64), ljsde.EUNSUPPORTED),      # valid for the method, no kernel
+    (dict(window=32, block=12), ljsde.EUNSUPPORTED),
+    (dict(fp64=True, splitbf16=True), ljsde.EINVAL),
+])
+def test_plan_validation(kwargs, code):
+    with pytest.raises(ljsde.LjsdeError) as e:
+        ljsde.plan(TILE, **kwargs)
+    assert e.value.code == code
+    assert ljsde.last_error()
+
+
+def test_plan_rejects_bad_codes_and_shapes():
+    bad = TILE.copy()
+    bad[1, 2] = 4
+    with pytest.raises(ljsde.LjsdeError) as e:
+        ljsde.plan(bad)
+    assert e.value.code == ljsde.EINVAL and "not in 0..3" in str(e.value)
+    L = ljsde.lib()
+    assert L.ljsde_plan(None, 4, 4, 32, 4, 10, 0.7, 0.5, ljsde.FP32) == ljsde.EINVAL
+    pat = np.ascontiguousarray(TILE)
+    ptr = pat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    assert L.ljsde_plan(ptr, 0, 4, 32, 4, 10, 0.7, 0.5, ljsde.FP32) == ljsde.EINVAL
+    assert L.ljsde_plan(ptr, 4, 4, 32, 4, 10, 0.7, 0.5, 0) == ljsde.EINVAL              # no precision
+    assert L.ljsde_plan(ptr, 4, 4, 32, 4, 10, 0.7, 0.5, 3) == ljsde.EINVAL              # both
+    assert L.ljsde_plan(ptr, 4, 4, 32, 4, 10, 0.7, 0.5, 2 | 64) == ljsde.EINVAL         # unknown flag
+
+
+def test_release_and_bad_ids():
+    pid = ljsde.plan(TILE)
+    assert ljsde.plan_info(pid) == dict(window=32, block=4, iters=100, flags=ljsde.FP32)
+    ljsde.release(pid)
+    for call in (lambda: ljsde.release(pid), lambda: ljsde.plan_info(pid), lambda: ljsde.class_map(pid, 8, 8),
+                 lambda: ljsde.set_energy_floor(pid, 0.1), lambda: ljsde.plan_info(-3)):
+        with pytest.raises(ljsde.LjsdeError) as e:
+            call()
+        assert e.value.code == ljsde.EBADID
+
+
+def test_energy_floor_validation():
+    pid = ljsde.plan(TILE)
+    ljsde.set_energy_floor(pid, 0.0)
+    ljsde.set_energy_floor(pid, 1e-6)
+    for bad in (-0.1, 1.0, float("nan")):
+        with pytest.raises(ljsde.LjsdeError) as e:
+            ljsde.set_energy_floor(pid, bad)
+        assert e.value.code == ljsde.EINVAL
+    ljsde.release(pid)
+
+
+def test_image_size_validation():
+    pid = ljsde.plan(TILE, block=8)
+    for rows, cols in ((0, 8), (8, -1), (6, 8), (8, 10)):   # sides must be multiples of B/2 = 4
+        with pytest.raises(ljsde.LjsdeError) as e:
+            ljsde.class_map(pid, rows, cols)
+        assert e.value.code == ljsde.EINVAL
+    assert ljsde.class_map(pid, 12, 8)[1].shape == (3 * 2,)     # 24x16 px in 8x8 blocks
+    ljsde.release(pid)
+
+
+@pytest.mark.skipif(not _no_gpu(), reason="checks the no-device error path")
+def test_reconstruct_without_device_reports_hip_error():
+    pid = ljsde.plan(TILE)
+    L = ljsde.lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.ljsde_reconstruct(fake, 16, 16, pid, fake, None) == ljsde.EHIP
+    assert "device" in ljsde.last_error()
+    assert L.ljsde_reconstruct(None, 16, 16, pid, fake, None) == ljsde.EINVAL
+    assert L.ljsde_synchronize(None) == ljsde.EHIP
+    ljsde.release(pid)
+
+
+# --------------------------------------------------------------------------
+# Classes: windows sharing a local measurement matrix (Sec. IV)
+# --------------------------------------------------------------------------
+
+def _interior_classes(period, B=4):
+    P = 2 * period
+    return (P // math.gcd(P, B)) ** 2
+
+
+@pytest.mark.parametrize("rows,period,interior,total", [
+    (512, 4, 4, 100),      # 512x512, 4x4-sensor tile
+    (2048, 8, 16, 144),    # 2048x2048, 8x8-sensor tile
+    (8192, 16, 64, 256),   # 8192x8192, 16x16-sensor tile (32 px, the paper's period)
+    (1200, 16, 64, 256),   # the paper's 1200x1200 frame
+])
+def test_class_counts(rows, period, interior, total):
+    pid = ljsde.plan(random_pattern(period, period, seed=1))
+    n, cls = ljsde.class_map(pid, rows // 2, rows // 2)
+    assert n == total
+    assert _interior_classes(period) == interior
+    nb = rows // 4
+    grid = cls.reshape(nb, nb)
+    assert len(np.unique(grid[4:-4, 4:-4])) == interior
+    ljsde.release(pid)
+
+
+def test_non_recurrent_pattern_gives_one_class_per_window():
+    case = make_case(64, 64, None, seed=0)
+    pid = ljsde.plan(case["tile"])
+    n, cls = ljsde.class_map(pid, 32, 32)
+    assert n == 256 and len(np.unique(cls)) == 256
+    ljsde.release(pid)
+
+
+@pytest.mark.parametrize("period,rows,cols,W,B", [(4, 40, 48, 32, 4), (3, 24, 36, 16, 4), (2, 32, 24, 32, 8)])
+def test_class_members_share_the_oracle_local_measurement_matrix(period, rows, cols, W, B):
+    tile = random_pattern(period, period + 1, seed=period)
+    pid = ljsde.plan(tile, window=W, block=B)
+    y = np.zeros((rows // 2, cols // 2))
+    n, cls = ljsde.class_map(pid, rows // 2, cols // 2)
+    nbj = cols // B
+    seen = {}
+    for w, c in enumerate(cls):
+        bi, bj = divmod(w, nbj)
+        _, codes, valid = O.local_window(y, tile, bi, bj, W, B)
+        key = np.where(valid, codes, -1)
+        if c in seen:
+            assert np.array_equal(seen[c], key)
+        else:
+            seen[c] = key
+    keys = {v.tobytes() for v in seen.values()}
+    assert len(keys) == n == len(seen)          # distinct classes are distinct matrices
+    for c, key in seen.items():
+        _, _, codes = ljsde.class_tables(pid, rows // 2, cols // 2, int(c), W)
+        assert np.array_equal(codes, key)
+    ljsde.release(pid)
+
+
+def _H(W):
+    """L-pixel responses H_o(sigma, rho) = sum of exp(i theta (a sigma + b rho))
+    over the three transparent quadrants (a, b) of orientation o."""
+    s = np.arange(W)
+    e = np.exp(2j * np.pi * s / W)
+    out = np.zeros((4, W, W), dtype=complex)
+    for o in range(4):
+        for a in (0, 1):
+            for b in (0, 1):
+                if (a, b) != (o >> 1, o & 1):
+                    out[o] += (e[:, None] ** a) * (e[None, :] ** b)
+    return out
+
+
+@pytest.mark.parametrize("W,bi,bj", [(32, 10, 9), (32, 0, 3), (16, 1, 5)])
+def test_class_tables_reproduce_dense_C_and_D(W, bi, bj):
+    """The library's FP64 S_o and D rebuild the oracle's dense C (eq. (14))
+    and D (eq. (13)) of the same local measurement matrix."""
+    tile = random_pattern(4, 4, seed=3)
+    rows = cols = 96
+    pid = ljsde.plan(tile, window=W, block=4)
+    n, cls = ljsde.class_map(pid, rows // 2, cols // 2)
+    c = int(cls[bi * (cols // 4) + bj])
+    S, D, codes = ljsde.class_tables(pid, rows // 2, cols // 2, c, W)
+    y = np.zeros((rows // 2, cols // 2))
+    _, ocodes, valid = O.local_window(y, tile, bi, bj, W, 4)
+    A = O.local_measurement_operator(ocodes, valid, W)
+    a = O.basis_responses(A, O.fourier_basis(W))
+    w = O.spatial_weights(W, 0.7) * valid.reshape(-1)
+    Bm, C, Dref = O.rljsde_precompute(a, w)
+    np.testing.assert_allclose(D, Dref, rtol=1e-12)
+    Ws = W // 2
+    H = _H(W).reshape(4, W * W)
+    S = S.reshape(Ws, Ws, 4)
+    sg = np.arange(W * W) // W
+    rh = np.arange(W * W) % W
+    # C[f, g] = sum_o conj(H_o(f)) H_o(g) S_o((sigma_f - sigma_g) mod Ws, (rho_f - rho_g) mod Ws)
+    dk = (sg[:, None] - sg[None, :]) % Ws
+    dl = (rh[:, None] - rh[None, :]) % Ws
+    Cf = sum(np.conj(H[o])[:, None] * H[o][None, :] * S[dk, dl, o] for o in range(4))
+    np.testing.assert_allclose(Cf, C, atol=1e-11 * np.abs(C).max())
+    ljsde.release(pid)
