@@ -37,9 +37,16 @@ in the design notes of the repository):
 * q = (1 - |f~| / (sqrt(2) W / 2))^2 with the aliased frequency magnitude
   |f~| = sqrt(min(s, W-s)^2 + min(r, W-r)^2) (Sec. IV only says it prefers low
   frequencies); ``q_mode='ones'`` gives q = 1.
-* One complex coefficient per iteration, as in eqs. (15)-(17); the argmax takes
-  the first maximum in sigma * W + rho order; frequencies with D <= 0 get
-  metric 0; the output is the real part of the central block of eq. (18).
+* One complex coefficient per iteration, as in eqs. (15)-(17); frequencies
+  with D <= 0 get metric 0; the output is the real part of the central block
+  of eq. (18).
+* Ties in the argmax of eqs. (10)/(11) are left open by the paper. They are
+  exact, not rare: conjugate partners tie whenever the residual is real, and
+  a sparse pattern can make two basis functions alias (their measurement
+  responses differ by a unit-modulus constant, so their metrics are equal).
+  Reading: every metric within a relative TIE_REL = 1e-10 of the maximum
+  counts as maximal and the lowest sigma * W + rho among them wins, so that
+  any FP64 evaluation order resolves a tie the same way.
 
 Parity pins (tests/test_oracle_*.py): brute-force weighted least squares on
 tiny windows, the closed-form energy decrease, exact recovery of a constant
@@ -198,9 +205,13 @@ class WindowTrace:
     energy0: float = 0.0
 
 
+TIE_REL = 1e-10
+
+
 def _select(metric: np.ndarray):
-    k = int(np.argmax(metric))              # first maximum in sigma*W + rho order
-    best = metric[k]
+    best = metric.max()
+    # lowest sigma*W + rho among the metrics tied (within TIE_REL) with the maximum
+    k = int(np.flatnonzero(metric >= best * (1.0 - TIE_REL))[0]) if best > 0 else 0
     if metric.size > 1 and best > 0:
         second = np.partition(metric, -2)[-2]
         gap = (best - second) / best

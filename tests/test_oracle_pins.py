@@ -171,6 +171,35 @@ def test_spatial_weight_is_isotropic_about_the_window_centre(W):
     np.testing.assert_allclose(w[h, h], 0.7 ** np.sqrt(2.0), rtol=1e-14)
 
 
+def test_aliased_basis_functions_tie_exactly_and_the_lowest_index_wins():
+    """With only orientations 1 and 3 (opaque quadrant in column 1) the
+    responses at sigma = 0 are orientation-independent, H(0, rho) = 2 + e^{i theta rho},
+    so a(0, rho + W/2) = a(0, rho) (2 - e^{i theta rho}) / (2 + e^{i theta rho}):
+    for rho = W/4 the factor has modulus 1 and the two metrics are equal. The
+    tie goes to the lower frequency index, in both formulations."""
+    W = 32
+    rng = np.random.default_rng(18)
+    codes = np.where(rng.random((W // 2, W // 2)) < 0.5, 1, 3)
+    valid = np.ones_like(codes, dtype=bool)
+    A = O.local_measurement_operator(codes, valid, W)
+    a = O.basis_responses(A, O.fourier_basis(W))
+    k1, k2 = 0 * W + W // 4, 0 * W + 3 * W // 4
+    ratio = a[:, k2] / a[:, k1]
+    np.testing.assert_allclose(ratio, ratio[0], rtol=1e-12)
+    assert abs(abs(ratio[0]) - 1.0) < 1e-14
+    eta, gam = np.mgrid[0:W, 0:W]
+    f_loc = 5.0 * np.exp(2j * np.pi * gam * (3 * W // 4) / W)      # the higher-index member
+    y_loc = np.tensordot(A, f_loc, axes=([1, 2], [0, 1]))
+    w = O.spatial_weights(W, 0.7)
+    q = O.frequency_weights(W, "ones")
+    trL = O.ljsde_window(y_loc, a, w, q, 6, 0.5)
+    Bm, C, D = O.rljsde_precompute(a, w)
+    trR = O.rljsde_window(y_loc, Bm, C, D, q, 6, 0.5)
+    for tr in (trL, trR):
+        assert tr.picks == [k1] * 6
+    np.testing.assert_allclose(trL.coeffs, trR.coeffs, atol=1e-12)
+
+
 # --------------------------------------------------------------------------
 # Exact recovery
 # --------------------------------------------------------------------------
