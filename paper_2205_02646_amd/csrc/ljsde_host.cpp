@@ -418,15 +418,23 @@ KJob make_job(const SizeSet &s, const void *y, void *out, int16_t *sel, long lon
 // Persistent batched launches
 // ---------------------------------------------------------------------------
 
+// Launch variant of a batch: windows per workgroup (same-class groups for
+// the FP64-state path; independent windows for the FP32-state path) and, for
+// the latter, windows per work grab.
 struct TuneChoice {
-    int waves_per_block = 1;
+    int waves_per_block = 4;
     int chunk = 2;
 };
 
 struct BatchState {
-    std::vector<std::tuple<int, int, int>> shape;  // (pattern id, Ms, Ns)
+    bool state_fp32 = false;            // all-FP32 variant (LJSDE_STATE_FP32)
     std::vector<KJob> host_jobs;
+    std::vector<const SizeSet *> sizes;  // host class maps of the jobs (owned by their plans)
+    std::string tune_key;
     KJob *d_jobs = nullptr;
+    WinGroup *d_groups = nullptr;
+    int ngroups = 0;
+    int groups_nw = 0;                  // group width the device list was built for
     unsigned int *d_counter = nullptr;
     long long total = 0;
     KParams params{};
@@ -440,6 +448,7 @@ struct BatchState {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (d_jobs) (void)hipFree(d_jobs);
+        if (d_groups) (void)hipFree(d_groups);
         if (d_counter) (void)hipFree(d_counter);
     }
 };
@@ -448,7 +457,7 @@ std::map<std::string, std::unique_ptr<BatchState>> g_batches;
 std::map<std::string, TuneChoice> g_tuned;
 hipStream_t g_capture_stream = nullptr;
 
-std::string tune_key(const Plan &p, long long total_windows, int n_classes) {
+std::string tune_key(const Plan &p, bool state_fp32, long long total_windows, int n_classes) {
     hipDeviceProp_t prop{};
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -458,8 +467,8 @@ std::string tune_key(const Plan &p, long long total_windows, int n_classes) {
     int wb = 0;
     while ((1LL << wb) < total_windows) ++wb;
     std::ostringstream os;
-    os << prop.gcnArchName << "/W" << p.W << "/B" << p.B << "/it" << p.iters << "/fp32/c" << bucket
-       << "/n" << wb;
+    os << prop.gcnArchName << "/W" << p.W << "/B" << p.B << "/it" << p.iters
+       << (state_fp32 ? "/fp32" : "/fp32s64") << "/c" << bucket << "/n" << wb;
     return os.str();
 }
 
@@ -474,10 +483,12 @@ void load_tune_cache() {
     std::string line;
     // one entry per line: "key" : [waves_per_block, chunk]
     while (std::getline(f, line)) {
-        size_t a = line.find('"'), b = line.find('"', a + 1), l = line.find('[', b), r = line.find(']', l);
-        if (a == std::string::npos || b == std::string::npos || l == std::string::npos ||
-            r == std::string::npos)
-            continue;
+        size_t a = line.find('"');
+        if (a == std::string::npos) continue;
+        size_t b = line.find('"', a + 1);
+        if (b == std::string::npos) continue;
+        size_t l = line.find('[', b);
+        if (l == std::string::npos || line.find(']', l) == std::string::npos) continue;
         TuneChoice c;
         if (sscanf(line.c_str() + l + 1, "%d , %d", &c.waves_per_block, &c.chunk) == 2 &&
             (c.waves_per_block == 1 || c.waves_per_block == 2 || c.waves_per_block == 4) && c.chunk >= 1 &&
@@ -500,13 +511,47 @@ void save_tune_cache() {
     f << "}\n";
 }
 
-int grid_for(int ws, const TuneChoice &c, int *grid) {
+int grid_for(const BatchState &b, const TuneChoice &c, int *grid) {
     int dev = 0, ncu = 0, blocks = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    int e = persistent_blocks_per_cu(ws, c.waves_per_block, &blocks);
+    const int e = b.state_fp32 ? persistent_blocks_per_cu(b.ws, c.waves_per_block, &blocks)
+                               : mixed_blocks_per_cu(b.ws, c.waves_per_block, &blocks);
     if (e != 0 || blocks <= 0) return fail(LJSDE_EHIP, "occupancy query failed (%d)", e);
     *grid = ncu * blocks;
+    return LJSDE_OK;
+}
+
+// Work list of the FP64-state path: per job and class, the windows of that
+// class in row-major order, cut into groups of at most nw (the waves of one
+// workgroup share the class's spectra in LDS).
+int build_groups(BatchState &b, int nw) {
+    if (b.groups_nw == nw && b.d_groups) return LJSDE_OK;
+    std::vector<WinGroup> groups;
+    for (size_t ji = 0; ji < b.sizes.size(); ++ji) {
+        const SizeSet &s = *b.sizes[ji];
+        const int nck = (int)s.colkeys.size();
+        std::vector<std::vector<int>> by_class(s.n_classes());
+        for (int bi = 0; bi < s.nbi; ++bi)
+            for (int bj = 0; bj < s.nbj; ++bj) by_class[s.rowcls[bi] * nck + s.colcls[bj]].push_back(bi * s.nbj + bj);
+        for (const auto &ws : by_class)
+            for (size_t k = 0; k < ws.size(); k += nw) {
+                WinGroup g{};
+                g.job = (int)ji;
+                g.count = (int)std::min<size_t>(nw, ws.size() - k);
+                for (int w = 0; w < 4; ++w) g.win[w] = ws[k + std::min(w, g.count - 1)];
+                groups.push_back(g);
+            }
+    }
+    if (b.d_groups) {
+        (void)hipFree(b.d_groups);
+        b.d_groups = nullptr;
+    }
+    int st = dev_alloc((void **)&b.d_groups, sizeof(WinGroup) * std::max<size_t>(groups.size(), 1));
+    if (st) return st;
+    HIP_TRY(hipMemcpy(b.d_groups, groups.data(), sizeof(WinGroup) * groups.size(), hipMemcpyHostToDevice));
+    b.ngroups = (int)groups.size();
+    b.groups_nw = nw;
     return LJSDE_OK;
 }
 
@@ -517,6 +562,7 @@ int prepare_batch(const ljsde_job *jobs, int n, void *stream, BatchState **out) 
     Plan *p0 = nullptr;
     int st = get_plan(jobs[0].pattern_id, &p0);
     if (st) return st;
+    const bool sf32 = (p0->flags & LJSDE_STATE_FP32) != 0;
     std::ostringstream key;
     for (int i = 0; i < n; ++i) {
         Plan *p = nullptr;
@@ -524,9 +570,9 @@ int prepare_batch(const ljsde_job *jobs, int n, void *stream, BatchState **out) 
         if (st) return st;
         if (p->fp64()) return fail(LJSDE_EUNSUPPORTED, "job %d: batched launches need FP32 plans", i);
         if (p->W != p0->W || p->B != p0->B || p->iters != p0->iters || p->gamma != p0->gamma ||
-            p->tau != p0->tau)
+            p->tau != p0->tau || ((p->flags & LJSDE_STATE_FP32) != 0) != sf32)
             return fail(LJSDE_EINVAL, "job %d: all plans of a batch need equal window, block, iters, "
-                                      "gamma and energy floor", i);
+                                      "gamma, energy floor and state precision", i);
         if (!jobs[i].measurements || !jobs[i].out)
             return fail(LJSDE_EINVAL, "job %d: null device pointer", i);
         st = check_size(*p, jobs[i].sensor_rows, jobs[i].sensor_cols);
@@ -540,6 +586,7 @@ int prepare_batch(const ljsde_job *jobs, int n, void *stream, BatchState **out) 
     auto &slot = g_batches[key.str()];
     if (!slot) {
         auto b = std::make_unique<BatchState>();
+        b->state_fp32 = sf32;
         long long total = 0;
         int n_classes = 0;
         for (int i = 0; i < n; ++i) {
@@ -551,6 +598,7 @@ int prepare_batch(const ljsde_job *jobs, int n, void *stream, BatchState **out) 
             st = ensure_device(*p, *s);
             if (st) return st;
             b->host_jobs.push_back(make_job(*s, nullptr, nullptr, nullptr, total));
+            b->sizes.push_back(s);
             total += (long long)s->nbi * s->nbj;
             n_classes = std::max(n_classes, s->n_classes());
         }
@@ -559,15 +607,21 @@ int prepare_batch(const ljsde_job *jobs, int n, void *stream, BatchState **out) 
         b->params = make_params(*p0);
         b->ws = p0->Ws;
         b->device = dev;
+        b->tune_key = tune_key(*p0, sf32, total, n_classes);
+        if (sf32) b->choice = TuneChoice{1, 2};
         st = dev_alloc((void **)&b->d_jobs, sizeof(KJob) * n);
         if (st) return st;
         st = dev_alloc((void **)&b->d_counter, sizeof(unsigned int));
         if (st) return st;
         load_tune_cache();
-        auto t = g_tuned.find(tune_key(*p0, total, n_classes));
+        auto t = g_tuned.find(b->tune_key);
         if (t != g_tuned.end()) b->choice = t->second;
-        st = grid_for(b->ws, b->choice, &b->grid);
+        st = grid_for(*b, b->choice, &b->grid);
         if (st) return st;
+        if (!sf32) {
+            st = build_groups(*b, b->choice.waves_per_block);
+            if (st) return st;
+        }
         slot = std::move(b);
     }
     BatchState *b = slot.get();
@@ -591,8 +645,12 @@ int prepare_batch(const ljsde_job *jobs, int n, void *stream, BatchState **out) 
 int launch_batch_eager(BatchState &b, const TuneChoice &c, int grid, void *stream) {
     int e = launch_reset_counter(b.d_counter, stream);
     if (e) return fail(LJSDE_EHIP, "reset launch: %s", hipGetErrorString((hipError_t)e));
-    e = launch_persistent_f32(b.params, b.d_jobs, (int)b.host_jobs.size(), b.total, b.d_counter, b.ws,
-                              c.waves_per_block, c.chunk, grid, stream);
+    if (b.state_fp32)
+        e = launch_persistent_f32(b.params, b.d_jobs, (int)b.host_jobs.size(), b.total, b.d_counter, b.ws,
+                                  c.waves_per_block, c.chunk, grid, stream);
+    else
+        e = launch_mixed_persistent(b.params, b.d_jobs, b.d_groups, b.ngroups, b.d_counter, b.ws,
+                                    c.waves_per_block, grid, stream);
     if (e) return fail(LJSDE_EHIP, "persistent launch: %s", hipGetErrorString((hipError_t)e));
     return LJSDE_OK;
 }
@@ -671,12 +729,12 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, i
     if (iters < 1) return fail(LJSDE_EINVAL, "iters %d must be >= 1", iters);
     if (!(rho > 0.0 && rho <= 1.0)) return fail(LJSDE_EINVAL, "rho %g must be in (0, 1]", rho);
     if (!(gamma > 0.0 && gamma < 2.0)) return fail(LJSDE_EINVAL, "gamma %g must be in (0, 2)", gamma);
-    const unsigned known = LJSDE_FP64 | LJSDE_FP32 | LJSDE_DFT_SPLITBF16 | LJSDE_Q_ONES;
+    const unsigned known = LJSDE_FP64 | LJSDE_FP32 | LJSDE_DFT_SPLITBF16 | LJSDE_Q_ONES | LJSDE_STATE_FP32;
     if (flags & ~known) return fail(LJSDE_EINVAL, "unknown flags 0x%x", flags & ~known);
     if (((flags & LJSDE_FP64) != 0) == ((flags & LJSDE_FP32) != 0))
         return fail(LJSDE_EINVAL, "exactly one of LJSDE_FP64 / LJSDE_FP32 is required");
-    if ((flags & LJSDE_DFT_SPLITBF16) && (flags & LJSDE_FP64))
-        return fail(LJSDE_EINVAL, "LJSDE_DFT_SPLITBF16 applies to FP32 plans only");
+    if ((flags & (LJSDE_DFT_SPLITBF16 | LJSDE_STATE_FP32)) && (flags & LJSDE_FP64))
+        return fail(LJSDE_EINVAL, "LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32 apply to FP32 plans only");
     if (!(window == 32 || window == 16))
         return fail(LJSDE_EUNSUPPORTED, "no kernel for window %d (have 16, 32)", window);
     if (!(block == 4 || block == 8))
@@ -728,7 +786,8 @@ static int reconstruct_impl(const void *y, int Ms, int Ns, int id, void *out, in
     if (p->fp64()) {
         e = launch_plain_f64(k, j, p->Ws, stream);
     } else if (sel) {
-        e = launch_plain_f32(k, j, p->Ws, stream);
+        e = (p->flags & LJSDE_STATE_FP32) ? launch_plain_f32(k, j, p->Ws, stream)
+                                          : launch_mixed_window(k, j, p->Ws, stream);
     } else {
         ljsde_job job{y, Ms, Ns, id, out};
         return run_batch(&job, 1, stream);
@@ -758,17 +817,24 @@ int ljsde_autotune(const ljsde_job *jobs, int n_jobs, void *stream) {
     BatchState *b = nullptr;
     int st = prepare_batch(jobs, n_jobs, stream, &b);
     if (st) return st;
-    const TuneChoice cands[] = {{1, 1}, {1, 2}, {1, 4}, {1, 8}, {2, 2}, {2, 4}, {4, 2}, {4, 4}};
+    std::vector<TuneChoice> cands;
+    if (b->state_fp32)
+        cands = {{1, 1}, {1, 2}, {1, 4}, {1, 8}, {2, 2}, {2, 4}, {4, 2}, {4, 4}};
+    else
+        cands = {{1, 1}, {2, 1}, {4, 1}};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     float best_ms = 1e30f;
     TuneChoice best = b->choice;
-    int best_grid = b->grid;
     for (const TuneChoice &c : cands) {
         int grid = 0;
-        st = grid_for(b->ws, c, &grid);
+        st = grid_for(*b, c, &grid);
         if (st) break;
+        if (!b->state_fp32) {
+            st = build_groups(*b, c.waves_per_block);
+            if (st) break;
+        }
         st = launch_batch_eager(*b, c, grid, stream);  // warm-up
         if (st) break;
         float total = 0;
@@ -786,25 +852,19 @@ int ljsde_autotune(const ljsde_job *jobs, int n_jobs, void *stream) {
         if (total / reps < best_ms) {
             best_ms = total / reps;
             best = c;
-            best_grid = grid;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st) return st;
     b->choice = best;
-    b->grid = best_grid;
-    Plan *p0 = nullptr;
-    get_plan(jobs[0].pattern_id, &p0);
-    int n_classes = 0;
-    for (int i = 0; i < n_jobs; ++i) {
-        Plan *p = nullptr;
-        get_plan(jobs[i].pattern_id, &p);
-        SizeSet *s = nullptr;
-        get_size(*p, jobs[i].sensor_rows, jobs[i].sensor_cols, &s);
-        n_classes = std::max(n_classes, s->n_classes());
+    st = grid_for(*b, best, &b->grid);
+    if (st) return st;
+    if (!b->state_fp32) {
+        st = build_groups(*b, best.waves_per_block);
+        if (st) return st;
     }
-    g_tuned[tune_key(*p0, b->total, n_classes)] = best;
+    g_tuned[b->tune_key] = best;
     save_tune_cache();
     st = capture_graph(*b);
     if (st) return st;
@@ -825,6 +885,8 @@ int ljsde_release(int pattern_id) {
     Plan *p = nullptr;
     int st = get_plan(pattern_id, &p);
     if (st) return st;
+    // work in flight may still read the plan's tables
+    if (p->d_consts) (void)hipDeviceSynchronize();
     // batches that reference this plan hold device pointers into its tables
     for (auto it = g_batches.begin(); it != g_batches.end();) {
         bool uses = false;
@@ -833,7 +895,6 @@ int ljsde_release(int pattern_id) {
         if (k.compare(0, pref.size(), pref) == 0 || k.find(";" + pref) != std::string::npos) uses = true;
         it = uses ? g_batches.erase(it) : std::next(it);
     }
-    if (p->d_consts) (void)hipDeviceSynchronize();
     for (auto &kv : p->sizes) {
         SizeSet &s = *kv.second;
         if (s.d_tables) (void)hipFree(s.d_tables);

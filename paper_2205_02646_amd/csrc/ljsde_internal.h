@@ -47,7 +47,14 @@ struct KJob {
     long long win_begin;           // first global window index of this job
 };
 
-// Launch wrappers (ljsde_kernels.hip). Return a hipError_t value.
+// Up to four windows of one job that share a class (persistent FP32 path).
+struct WinGroup {
+    int job;
+    int count;
+    int win[4];  // window index inside the job, row-major block order
+};
+
+// Launch wrappers (ljsde_kernels.hip, ljsde_mixed.hip). Return a hipError_t value.
 int launch_plain_f64(const KParams &p, const KJob &job, int ws, void *stream);
 int launch_plain_f32(const KParams &p, const KJob &job, int ws, void *stream);
 int launch_reset_counter(unsigned int *counter, void *stream);
@@ -56,5 +63,10 @@ int launch_persistent_f32(const KParams &p, const KJob *d_jobs, int njobs, long 
                           int grid, void *stream);
 int persistent_blocks_per_cu(int ws, int waves_per_block, int *blocks);
 size_t lds_bytes_per_wave(int ws, bool fp64);
+int launch_mixed_window(const KParams &p, const KJob &job, int ws, void *stream);
+int launch_mixed_persistent(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, int ngroups,
+                            unsigned int *counter, int ws, int nw, int grid, void *stream);
+int mixed_blocks_per_cu(int ws, int nw, int *blocks);
+size_t mixed_lds_bytes(int ws, int nw);
 
 }  // namespace ljsde

@@ -23,25 +23,10 @@
 // q / D and the twiddles live in VGPRs.
 #include <hip/hip_runtime.h>
 
+#include "ljsde_device.h"
 #include "ljsde_internal.h"
 
 namespace ljsde {
-
-template <typename T>
-struct C2 {
-    T re, im;
-};
-
-__device__ __forceinline__ void wave_lds_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
 
 template <typename T>
 __device__ __forceinline__ T load_qd(const double *qd64, const float *qd32, int i);
@@ -186,6 +171,9 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
     for (int o = 0; o < 4; ++o) g4[o] = {T(0), T(0)};
     int u = 0, v = 0;
     int nu_done = 0;
+    // FP64: ties within TIE_REL go to the lowest index; the FP32 state
+    // variant compares strictly (its rounding is far above TIE_REL)
+    const T eps = sizeof(T) == 8 ? T(TIE_REL) : T(0);
 
 #pragma unroll 1
     for (int nu = 0; nu < p.iters; ++nu) {
@@ -227,20 +215,19 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
             const T m01 = (r01.re * r01.re + r01.im * r01.im) * qd[t][1];
             const T m10 = (r10.re * r10.re + r10.im * r10.im) * qd[t][2];
             const T m11 = (r11.re * r11.re + r11.im * r11.im) * qd[t][3];
-            if (m00 > best0) { best0 = m00; code0 = 2 * t; }
-            if (m01 > best0) { best0 = m01; code0 = 2 * t + 1; }
-            if (m10 > best1) { best1 = m10; code1 = 2 * t; }
-            if (m11 > best1) { best1 = m11; code1 = 2 * t + 1; }
+            tie_keep<T>(best0, code0, m00, 2 * t, eps);
+            tie_keep<T>(best0, code0, m01, 2 * t + 1, eps);
+            tie_keep<T>(best1, code1, m10, 2 * t, eps);
+            tie_keep<T>(best1, code1, m11, 2 * t + 1, eps);
         }
-        T best;
-        int code, a;
-        if (best1 > best0) { best = best1; code = code1; a = 1; }
-        else { best = best0; code = code0; a = 0; }
-        int idx = (kap0 + (code >> 1) + WS * a) * W + lam + WS * (code & 1);
+        // a = 1 frequencies have higher indices than all a = 0 ones
+        T best = best0;
+        int idx = (kap0 + (code0 >> 1)) * W + lam + WS * (code0 & 1);
+        tie_merge<T>(best, idx, best1, (kap0 + (code1 >> 1) + WS) * W + lam + WS * (code1 & 1), eps);
         for (int o = 32; o > 0; o >>= 1) {
             const T ob = __shfl_xor(best, o);
             const int oid = __shfl_xor(idx, o);
-            if (ob > best || (ob == best && oid < idx)) { best = ob; idx = oid; }
+            tie_merge<T>(best, idx, ob, oid, eps);
         }
         idx = __builtin_amdgcn_readfirstlane(idx);
         u = idx / W;

@@ -1,0 +1,431 @@
+// FP32-search RL-JSDE kernels for gfx950 with an FP64 loop state.
+//
+// The per-window state is the factorised projected residual P_o(k, l) (one
+// (W/2)-point DFT of the weighted residual per opaque-quadrant orientation,
+// see ljsde_kernels.hip). Here it is kept in FP64 and updated with FP64 FMAs
+// (full rate on CDNA, like unpacked FP32), while the projection through the
+// L-pixel responses, the eq. (11) metric and the argmax search run in FP32.
+// Greedy selection is discontinuous: when the two best FP32 metrics of an
+// iteration are closer than a relative NEAR_TIE, the iteration's selection is
+// re-decided from the FP64 state in FP64 (first maximum in sigma * W + rho
+// order). The step of eqs. (15)-(16), the energy of eq. (8) and the
+// back-transform of eq. (18) are FP64.
+//
+// A workgroup holds NW wavefronts that model NW windows of the same class
+// (same local measurement matrix), so the class's FP64 weighted-mask spectra
+// S_o are staged in LDS once per group and shared.
+#include <hip/hip_runtime.h>
+
+#include "ljsde_device.h"
+#include "ljsde_internal.h"
+
+namespace ljsde {
+
+constexpr float NEAR_TIE = 1e-4f;
+
+template <int WS>
+struct MixedLds {
+    static constexpr int NPOS = WS * WS;
+    static constexpr int W = 2 * WS;
+    static constexpr int QPL = NPOS / 64;
+    // per workgroup: S_o [4][NPOS] complex double; per-lane q/D [QPL][64][4] float and
+    // projection twiddles [QPL][64][4] float; the twiddle tables; a work slot
+    static constexpr size_t offQd = (size_t)NPOS * 64;
+    static constexpr size_t offTw = offQd + (size_t)QPL * 64 * 16;
+    static constexpr size_t offTab = offTw + (size_t)QPL * 64 * 16;
+    static constexpr size_t offSlot = offTab + (size_t)(2 * WS + 2 * W) * 8;
+    static constexpr size_t shared_bytes = offSlot + 64;
+    // per wavefront: DFT stage [NPOS] complex double, w*y [NPOS] double, codes [NPOS]
+    static constexpr size_t wave_bytes = (size_t)NPOS * 16 + (size_t)NPOS * 8 + NPOS;
+    static constexpr size_t bytes(int nw) { return shared_bytes + nw * wave_bytes; }
+};
+
+// R(a, b) for the four frequencies (k + Ws a, l + Ws b) of one position:
+// R = sum_q (-1)^(qa a + qb b) e^{-i theta (qa k + qb l)} (sum_o P_o - P_q).
+template <typename T>
+__device__ __forceinline__ void project4(const C2<T> P[4], C2<T> tl, C2<T> tk, C2<T> tkl, C2<T> R[4]) {
+    const C2<T> sp = {P[0].re + P[1].re + P[2].re + P[3].re, P[0].im + P[1].im + P[2].im + P[3].im};
+    const C2<T> q0 = {sp.re - P[0].re, sp.im - P[0].im};
+    const C2<T> q1 = {sp.re - P[1].re, sp.im - P[1].im};
+    const C2<T> q2 = {sp.re - P[2].re, sp.im - P[2].im};
+    const C2<T> q3 = {sp.re - P[3].re, sp.im - P[3].im};
+    const C2<T> u1 = {tl.re * q1.re - tl.im * q1.im, tl.re * q1.im + tl.im * q1.re};
+    const C2<T> u2 = {tk.re * q2.re - tk.im * q2.im, tk.re * q2.im + tk.im * q2.re};
+    const C2<T> u3 = {tkl.re * q3.re - tkl.im * q3.im, tkl.re * q3.im + tkl.im * q3.re};
+    const C2<T> s1 = {q0.re + u3.re, q0.im + u3.im}, d1 = {q0.re - u3.re, q0.im - u3.im};
+    const C2<T> s2 = {u1.re + u2.re, u1.im + u2.im}, d2 = {u1.re - u2.re, u1.im - u2.im};
+    R[0] = {s1.re + s2.re, s1.im + s2.im};  // (a, b) = (0, 0)
+    R[1] = {d1.re - d2.re, d1.im - d2.im};  // (0, 1)
+    R[2] = {d1.re + d2.re, d1.im + d2.im};  // (1, 0)
+    R[3] = {s1.re - s2.re, s1.im - s2.im};  // (1, 1)
+}
+
+template <int WS>
+__device__ __forceinline__ void process_window_mixed(const KParams &p, const KJob &j, int bi, int bj,
+                                                     long long win_local, char *wlds, const char *glds) {
+    using LL = MixedLds<WS>;
+    const double *Sl = (const double *)glds;
+    const float *qdl = (const float *)(glds + LL::offQd);
+    const float *twl = (const float *)(glds + LL::offTw);
+    const double *tab = (const double *)(glds + LL::offTab);
+    constexpr int W = 2 * WS;
+    constexpr int QPL = WS * WS / 64;
+    constexpr int NPOS = WS * WS;
+    int lane = threadIdx.x & 63;
+    // opaque per window: stops lane-derived addressing from being hoisted out
+    // of the persistent loop and kept live (in VGPRs) across all windows
+    asm volatile("" : "+v"(lane));
+    const int lam = lane % WS;
+    const int kap0 = (lane / WS) * QPL;
+    const double *dft = tab;           // [WS][2] exp(-2 pi i k / WS)
+    const double *ew = tab + 2 * WS;   // [W][2]  exp(+2 pi i k / W)
+
+    const int cls = j.rowcls[bi] * j.ncolk + j.colcls[bj];
+    const unsigned char *tb = j.tables + (size_t)cls * p.lay.stride;
+    const double *qD64 = (const double *)(tb + p.lay.offQD64);
+    const double *invD = (const double *)(tb + p.lay.offInvD);
+    const signed char *codes = (const signed char *)(tb + p.lay.offCodes);
+
+    C2<double> *stage = (C2<double> *)wlds;
+    double *X = (double *)(wlds + NPOS * 16);
+    signed char *Cd = (signed char *)(wlds + NPOS * 24);
+
+    wave_lds_fence();
+
+    // ---- gather the sensor tile, weighted (absent pixels -> 0) -------------
+    const int rs = (p.B * bi - p.off) / 2;
+    const int cs = (p.B * bj - p.off) / 2;
+    const float *Y = (const float *)j.y;
+    double e0 = 0.0;
+    for (int m = lane; m < NPOS; m += 64) {
+        const int ip = m / WS, jp = m % WS;
+        const int gi = rs + ip, gj = cs + jp;
+        signed char code = codes[m];
+        double x = 0.0;
+        if (code >= 0 && gi >= 0 && gi < j.Ms && gj >= 0 && gj < j.Ns) {
+            const double yv = (double)Y[(size_t)gi * j.Ns + gj];
+            x = p.c.w[m] * yv;
+            e0 += x * yv;
+        } else {
+            code = -1;
+        }
+        X[m] = x;
+        Cd[m] = code;
+    }
+    e0 = uniform_f64(wave_sum(e0));
+    wave_lds_fence();
+
+    // ---- FP64 orientation-masked DFT, one orientation at a time -----------
+    C2<double> P[QPL][4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {  // unrolled: P must be indexed statically
+#pragma unroll 1
+        for (int s = 0; s < QPL; ++s) {
+            const int ip = kap0 + s;
+            C2<double> acc = {0.0, 0.0};
+#pragma unroll 4
+            for (int jp = 0; jp < WS; ++jp) {
+                const double x = (Cd[ip * WS + jp] == o) ? X[ip * WS + jp] : 0.0;
+                const int k = (jp * lam) & (WS - 1);
+                acc.re += x * dft[2 * k];
+                acc.im += x * dft[2 * k + 1];
+            }
+            stage[ip * WS + lam] = acc;
+        }
+        wave_lds_fence();
+#pragma unroll
+        for (int t = 0; t < QPL; ++t) {
+            const int kap = kap0 + t;
+            C2<double> acc = {0.0, 0.0};
+#pragma unroll 4
+            for (int ip = 0; ip < WS; ++ip) {
+                const C2<double> a = stage[ip * WS + lam];
+                const int k = (ip * kap) & (WS - 1);
+                const double tr = dft[2 * k], ti = dft[2 * k + 1];
+                acc.re += a.re * tr - a.im * ti;
+                acc.im += a.re * ti + a.im * tr;
+            }
+            P[t][o] = acc;
+        }
+        wave_lds_fence();
+    }
+
+    const C2<float> tl = {(float)ew[2 * lam], (float)-ew[2 * lam + 1]};
+
+    const int BB = p.B * p.B;
+    const int oi = lane / p.B, oj = lane % p.B;
+    double outacc = 0.0;
+    double E = e0;
+    double gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
+    int u = 0, v = 0;
+    int nu_done = 0;
+
+#pragma unroll 1
+    for (int nu = 0; nu < p.iters; ++nu) {
+        unsigned kb = 0u, ks = 0u;
+#pragma unroll
+        for (int t = 0; t < QPL; ++t) {
+            const int kap = kap0 + t;
+            if (nu > 0) {
+                // eq. (17), factorised: subtract the shifted weighted-mask spectra
+                const int pos = ((kap - u) & (WS - 1)) * WS + ((lam - v) & (WS - 1));
+                const C2<double> *s = (const C2<double> *)Sl + pos;
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    const C2<double> so = s[o * NPOS];
+                    P[t][o].re = fma(-gre[o], so.re, fma(gim[o], so.im, P[t][o].re));
+                    P[t][o].im = fma(-gre[o], so.im, fma(-gim[o], so.re, P[t][o].im));
+                }
+            }
+            C2<float> Pf[4], R[4];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) Pf[o] = {(float)P[t][o].re, (float)P[t][o].im};
+            const float4 q4 = *(const float4 *)(qdl + (t * 64 + lane) * 4);
+            const float4 t4 = *(const float4 *)(twl + (t * 64 + lane) * 4);
+            project4<float>(Pf, tl, C2<float>{t4.x, t4.y}, C2<float>{t4.z, t4.w}, R);
+            const float qd[4] = {q4.x, q4.y, q4.z, q4.w};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float m = (R[c].re * R[c].re + R[c].im * R[c].im) * qd[c];
+                const unsigned key = (__float_as_uint(m) & ~15u) | (unsigned)(t * 4 + c);
+                ks = umed3(kb, ks, key);
+                kb = max(kb, key);
+            }
+            __builtin_amdgcn_sched_barrier(0);  // one position at a time: bounds register pressure
+        }
+        unsigned M = kb, S2 = ks;
+        wave_top2_u32(M, S2);
+        const float fM = __uint_as_float(M & ~15u), fS = __uint_as_float(S2 & ~15u);
+        int idx;
+        if (fS < fM * (1.0f - NEAR_TIE)) {
+            // unique FP32 winner: its lane and in-lane code
+            const unsigned long long hit = __ballot(kb == M);
+            const int L = __builtin_ctzll(hit);
+            const int code = (int)(M & 15u);
+            const int t = code >> 2, a = (code >> 1) & 1, b = code & 1;
+            idx = ((L / WS) * QPL + t + WS * a) * W + (L % WS) + WS * b;
+        } else {
+            // near tie: decide in FP64 from the FP64 state
+            double b0 = -1.0, b1 = -1.0;
+            int i0 = 0, i1 = 0;
+#pragma unroll
+            for (int t = 0; t < QPL; ++t) {
+                const int kap = kap0 + t;
+                const C2<double> dtk = {ew[2 * kap], -ew[2 * kap + 1]};
+                const C2<double> dtkl = {ew[2 * (kap + lam)], -ew[2 * (kap + lam) + 1]};
+                const C2<double> dtl = {ew[2 * lam], -ew[2 * lam + 1]};
+                C2<double> R[4];
+                project4<double>(P[t], dtl, dtk, dtkl, R);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int a = c >> 1, b = c & 1;
+                    int f = (kap + WS * a) * W + lam + WS * b;
+                    asm volatile("" : "+v"(f));  // keep the (rare) table addressing inside this branch
+                    const double m = (R[c].re * R[c].re + R[c].im * R[c].im) * qD64[f];
+                    if (a == 0) tie_keep<double>(b0, i0, m, f, TIE_REL);
+                    else tie_keep<double>(b1, i1, m, f, TIE_REL);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            double best = b0;
+            idx = i0;
+            tie_merge<double>(best, idx, b1, i1, TIE_REL);
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ob = __shfl_xor(best, o);
+                const int oid = __shfl_xor(idx, o);
+                tie_merge<double>(best, idx, ob, oid, TIE_REL);
+            }
+        }
+        idx = __builtin_amdgcn_readfirstlane(idx);
+        u = idx / W;
+        v = idx % W;
+
+        // L-pixel responses H_o(u, v) of the selected basis function
+        const double eur = ew[2 * u], eui = ew[2 * u + 1];
+        const double evr = ew[2 * v], evi = ew[2 * v + 1];
+        const int uv = (u + v) & (W - 1);
+        const double hbr = (1.0 + eur) * (1.0 + evr) - eui * evi;
+        const double hbi = (1.0 + eur) * evi + eui * (1.0 + evr);
+        const double Hr[4] = {hbr - 1.0, hbr - evr, hbr - eur, hbr - ew[2 * uv]};
+        const double Hi[4] = {hbi, hbi - evi, hbi - eui, hbi - ew[2 * uv + 1]};
+
+        // R_uv in FP64 from the owner lane
+        const int ku = u & (WS - 1), lv = v & (WS - 1);
+        const int tu = ku % QPL;
+        const int owner = (ku / QPL) * WS + lv;
+        double rr = 0.0, ri = 0.0;
+#pragma unroll
+        for (int t = 0; t < QPL; ++t) {
+            if (tu == t) {
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    rr += Hr[o] * P[t][o].re + Hi[o] * P[t][o].im;
+                    ri += Hr[o] * P[t][o].im - Hi[o] * P[t][o].re;
+                }
+            }
+        }
+        rr = readlane_f64(rr, owner);
+        ri = readlane_f64(ri, owner);
+
+        // eqs. (15)-(16) and the energy of eq. (8), FP64
+        const double id = invD[idx];
+        const double gr = p.gamma * rr * id, gi = p.gamma * ri * id;
+        E = uniform_f64(E - p.ecoef * (rr * rr + ri * ri) * id);
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            gre[o] = uniform_f64(gr * Hr[o] - gi * Hi[o]);
+            gim[o] = uniform_f64(gr * Hi[o] + gi * Hr[o]);
+        }
+        // eq. (18) on the central block, pick by pick
+        if (lane < BB) {
+            const int ph = ((p.off + oi) * u + (p.off + oj) * v) & (W - 1);
+            outacc += gr * ew[2 * ph] - gi * ew[2 * ph + 1];
+        }
+        if (j.sel != nullptr && lane == 0) j.sel[win_local * p.iters + nu] = (int16_t)idx;
+        nu_done = nu + 1;
+        if (p.tau > 0.0 && E <= p.tau * e0) break;
+    }
+    if (j.sel != nullptr)
+        for (int nu = nu_done + lane; nu < p.iters; nu += 64) j.sel[win_local * p.iters + nu] = -1;
+    if (lane < BB) {
+        float *O = (float *)j.out;
+        const size_t row = (size_t)(p.B * bi + oi);
+        O[row * (size_t)(2 * j.Ns) + (size_t)(p.B * bj + oj)] = (float)outacc;
+    }
+}
+
+// Stage a class's FP64 spectra and per-lane q/D into LDS (whole workgroup);
+// with `with_tab` also the class-independent twiddles.
+template <int WS>
+__device__ __forceinline__ void stage_tables(const KParams &p, const KJob &j, int cls, char *glds, bool with_tab) {
+    using LL = MixedLds<WS>;
+    constexpr int NPOS = WS * WS, W = 2 * WS, QPL = NPOS / 64;
+    double *Sl = (double *)glds;
+    float *qdl = (float *)(glds + LL::offQd);
+    const unsigned char *tb = j.tables + (size_t)cls * p.lay.stride;
+    const double *S64 = (const double *)(tb + p.lay.offS);
+    const float *qD32 = (const float *)(tb + p.lay.offQD32);
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));  // not hoisted out of the persistent loop
+    // table order [pos][o][re, im] -> LDS order [o][pos][re, im]: for a fixed o the
+    // lanes of a row read consecutive 16-byte entries (no bank conflicts)
+    for (int e = tid; e < NPOS * 8; e += blockDim.x) {
+        const int pos = e >> 3, o = (e >> 1) & 3, c = e & 1;
+        Sl[(o * NPOS + pos) * 2 + c] = S64[e];
+    }
+    // q/D of the 4 frequencies (k + Ws a, l + Ws b) of each lane's positions
+    for (int e = tid; e < QPL * 64 * 4; e += blockDim.x) {
+        const int c = e & 3, ln = (e >> 2) & 63, t = e >> 8;
+        const int kap = (ln / WS) * QPL + t, lam = ln % WS;
+        qdl[e] = qD32[(kap + WS * (c >> 1)) * W + lam + WS * (c & 1)];
+    }
+    if (with_tab) {
+        float *twl = (float *)(glds + LL::offTw);
+        double *tab = (double *)(glds + LL::offTab);
+        for (int e = threadIdx.x; e < 2 * WS; e += blockDim.x) tab[e] = p.c.dft[e];
+        for (int e = threadIdx.x; e < 4 * WS; e += blockDim.x) tab[2 * WS + e] = p.c.ew[e];
+        // e^{-i theta k} and e^{-i theta (k + l)} per lane position
+        for (int e = threadIdx.x; e < QPL * 64; e += blockDim.x) {
+            const int ln = e & 63, t = e >> 6;
+            const int kap = (ln / WS) * QPL + t, lam = ln % WS;
+            twl[e * 4 + 0] = (float)p.c.ew[2 * kap];
+            twl[e * 4 + 1] = (float)-p.c.ew[2 * kap + 1];
+            twl[e * 4 + 2] = (float)p.c.ew[2 * (kap + lam)];
+            twl[e * 4 + 3] = (float)-p.c.ew[2 * (kap + lam) + 1];
+        }
+    }
+}
+
+// One window per workgroup (used for selection diagnostics).
+template <int WS>
+__global__ __launch_bounds__(64) void mixed_window_kernel(KParams p, KJob j) {
+    extern __shared__ __align__(16) char lds[];
+    using L = MixedLds<WS>;
+    const long long w = blockIdx.x;
+    const long long nwin = (long long)j.nbi * j.nbj;
+    if (w >= nwin) return;
+    const int bi = (int)(w / j.nbj), bj = (int)(w % j.nbj);
+    stage_tables<WS>(p, j, j.rowcls[bi] * j.ncolk + j.colcls[bj], lds, true);
+    __syncthreads();
+    process_window_mixed<WS>(p, j, bi, bj, w, lds + L::shared_bytes, lds);
+}
+
+// Persistent: workgroups pull groups of up to NW same-class windows.
+template <int WS, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void mixed_persistent_kernel(KParams p, const KJob *__restrict__ jobs,
+                                                                   const WinGroup *__restrict__ groups,
+                                                                   int ngroups, unsigned int *counter) {
+    extern __shared__ __align__(16) char lds[];
+    using L = MixedLds<WS>;
+    int *slot = (int *)(lds + L::offSlot);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    char *wl = lds + L::shared_bytes + (size_t)wave * L::wave_bytes;
+    bool first = true;
+    for (;;) {
+        if (threadIdx.x == 0) *slot = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        // the group index is workgroup-uniform: keep it (and all that derives
+        // from it) in scalar registers
+        const int gi = __builtin_amdgcn_readfirstlane(*slot);
+        if (gi >= ngroups) break;
+        const int gjob = groups[gi].job, gcount = groups[gi].count;
+        const KJob J = jobs[gjob];
+        const int w0 = groups[gi].win[0];
+        const int cls = J.rowcls[w0 / J.nbj] * J.ncolk + J.colcls[w0 % J.nbj];
+        stage_tables<WS>(p, J, cls, lds, first);
+        first = false;
+        __syncthreads();
+        if (wave < gcount) {
+            const int lw = __builtin_amdgcn_readfirstlane(groups[gi].win[wave]);
+            process_window_mixed<WS>(p, J, lw / J.nbj, lw % J.nbj, lw, wl, lds);
+        }
+        __syncthreads();
+    }
+}
+
+size_t mixed_lds_bytes(int ws, int nw) { return ws == 16 ? MixedLds<16>::bytes(nw) : MixedLds<8>::bytes(nw); }
+
+int launch_mixed_window(const KParams &p, const KJob &job, int ws, void *stream) {
+    const long long nwin = (long long)job.nbi * job.nbj;
+    if (nwin <= 0) return 0;
+    const size_t lds = mixed_lds_bytes(ws, 1);
+    if (ws == 16)
+        mixed_window_kernel<16><<<dim3((unsigned)nwin), dim3(64), lds, (hipStream_t)stream>>>(p, job);
+    else
+        mixed_window_kernel<8><<<dim3((unsigned)nwin), dim3(64), lds, (hipStream_t)stream>>>(p, job);
+    return (int)hipGetLastError();
+}
+
+template <int WS, int NW>
+static int launch_mp(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, int ngroups,
+                     unsigned int *counter, int grid, void *stream) {
+    const size_t lds = MixedLds<WS>::bytes(NW);
+    mixed_persistent_kernel<WS, NW><<<dim3(grid), dim3(64 * NW), lds, (hipStream_t)stream>>>(p, d_jobs, d_groups,
+                                                                                            ngroups, counter);
+    return (int)hipGetLastError();
+}
+
+int launch_mixed_persistent(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, int ngroups,
+                            unsigned int *counter, int ws, int nw, int grid, void *stream) {
+    if (ws == 16) {
+        if (nw == 1) return launch_mp<16, 1>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
+        if (nw == 2) return launch_mp<16, 2>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
+        return launch_mp<16, 4>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
+    }
+    if (nw == 1) return launch_mp<8, 1>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
+    if (nw == 2) return launch_mp<8, 2>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
+    return launch_mp<8, 4>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
+}
+
+template <int WS, int NW>
+static int occ_mp(int *blocks) {
+    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, mixed_persistent_kernel<WS, NW>, 64 * NW,
+                                                             MixedLds<WS>::bytes(NW));
+}
+
+int mixed_blocks_per_cu(int ws, int nw, int *blocks) {
+    if (ws == 16) return nw == 1 ? occ_mp<16, 1>(blocks) : nw == 2 ? occ_mp<16, 2>(blocks) : occ_mp<16, 4>(blocks);
+    return nw == 1 ? occ_mp<8, 1>(blocks) : nw == 2 ? occ_mp<8, 2>(blocks) : occ_mp<8, 4>(blocks);
+}
+
+}  // namespace ljsde

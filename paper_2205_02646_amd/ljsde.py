@@ -26,6 +26,7 @@ FP64 = 1
 FP32 = 2
 DFT_SPLITBF16 = 4
 Q_ONES = 8
+STATE_FP32 = 16
 
 _NAMES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOMEM: "ENOMEM", EHIP: "EHIP", EBADID: "EBADID"}
 
@@ -93,12 +94,14 @@ def version() -> int:
 
 
 def plan(pattern, window: int = 32, block: int = 4, iters: int = 100, rho: float = 0.7,
-         gamma: float = 0.5, fp64: bool = False, splitbf16: bool = False, q_ones: bool = False) -> int:
+         gamma: float = 0.5, fp64: bool = False, splitbf16: bool = False, q_ones: bool = False,
+         state_fp32: bool = False) -> int:
     """Register a plan for an opaque-quadrant pattern tile; returns its id."""
     pat = np.ascontiguousarray(np.asarray(pattern, dtype=np.uint8))
     if pat.ndim != 2:
         raise ValueError("pattern must be 2-D")
-    flags = (FP64 if fp64 else FP32) | (DFT_SPLITBF16 if splitbf16 else 0) | (Q_ONES if q_ones else 0)
+    flags = ((FP64 if fp64 else FP32) | (DFT_SPLITBF16 if splitbf16 else 0) | (Q_ONES if q_ones else 0)
+             | (STATE_FP32 if state_fp32 else 0))
     return _check(lib().ljsde_plan(pat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), pat.shape[0],
                                    pat.shape[1], window, block, iters, rho, gamma, flags))
 

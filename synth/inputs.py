@@ -41,38 +41,60 @@ def _streams(seed: int):
     return [np.random.default_rng(s) for s in ss.spawn(4)]
 
 
-def _fill_polygon(rows: int, cols: int, verts: np.ndarray) -> np.ndarray:
-    """Boolean mask of pixel centres inside a simple polygon (even-odd rule)."""
-    yy, xx = np.mgrid[0:rows, 0:cols]
-    py = yy + 0.5
-    px = xx + 0.5
-    inside = np.zeros((rows, cols), dtype=bool)
+def _fill_polygon(rows, cols, verts, r0=0, c0=0):
+    """Boolean mask of pixel centres inside a simple polygon (even-odd rule),
+    evaluated on the pixels [r0, r0 + rows) x [c0, c0 + cols) of the image.
+
+    Scanline form: on the row through py = row + 0.5 a pixel centre px is
+    inside when an odd number of edge crossings x satisfies x <= px (edges are
+    half-open in y). With the crossings sorted, that is
+    px in [x1, x2) u [x3, x4) u ..., i.e. columns ceil(xa - 1/2) .. ceil(xb - 1/2) - 1.
+    """
+    py = np.arange(r0, r0 + rows) + 0.5
     n = len(verts)
+    xs = np.full((rows, n), np.inf)
     for k in range(n):
         y0, x0 = verts[k]
         y1, x1 = verts[(k + 1) % n]
         if y0 == y1:
             continue
         cond = (py >= min(y0, y1)) & (py < max(y0, y1))
-        xint = x0 + (py - y0) * (x1 - x0) / (y1 - y0)
-        inside ^= cond & (px < xint)
-    return inside
+        xs[cond, k] = x0 + (py[cond] - y0) * (x1 - x0) / (y1 - y0)
+    xs.sort(axis=1)
+    diff = np.zeros((rows, cols + 1), dtype=np.int16)
+    ridx = np.arange(rows)
+    for k in range(0, n - 1, 2):
+        xa, xb = xs[:, k], xs[:, k + 1]
+        ok = np.isfinite(xa) & np.isfinite(xb)
+        start = np.clip(np.ceil(xa[ok] - 0.5) - c0, 0, cols).astype(np.intp)
+        end = np.clip(np.ceil(xb[ok] - 0.5) - c0, 0, cols).astype(np.intp)
+        np.add.at(diff, (ridx[ok], start), 1)
+        np.add.at(diff, (ridx[ok], end), -1)
+    return np.cumsum(diff[:, :cols], axis=1) > 0
 
 
-def synthetic_image(rows: int, cols: int, seed: int = 0, noise_sigma: float = 0.0):
+def synthetic_image(rows: int, cols: int, seed: int = 0, noise_sigma: float = 0.0, region=None):
     """Return ``(clean, observed)`` float64 images of shape (rows, cols).
 
     ``observed`` equals ``clean`` plus N(0, noise_sigma^2) noise (no re-clip).
+    ``region = (r0, r1, c0, c1)`` evaluates only that part of the full image
+    (same values as the corresponding slice of the full image; the noise of a
+    region is drawn for the region alone, so use it with noise_sigma = 0).
     """
     g_img, g_poly, _, g_noise = _streams(seed)
-    eta, gam = np.mgrid[0:rows, 0:cols].astype(np.float64)
-    f = np.full((rows, cols), 128.0)
+    r0, r1, c0, c1 = (0, rows, 0, cols) if region is None else region
+    eta = np.arange(r0, r1, dtype=np.float64)
+    gam = np.arange(c0, c1, dtype=np.float64)
+    f = np.full((r1 - r0, c1 - c0), 128.0)
     for _ in range(8):
         amp = g_img.uniform(0.0, 40.0)
         th = g_img.uniform(0.0, np.pi)
         phi = g_img.uniform(0.02, 0.45)
         psi = g_img.uniform(0.0, 2.0 * np.pi)
-        f += amp * np.sin(2.0 * np.pi * phi * (eta * np.cos(th) + gam * np.sin(th)) + psi)
+        a = 2.0 * np.pi * phi * np.cos(th) * eta
+        b = 2.0 * np.pi * phi * np.sin(th) * gam + psi
+        # sin(a + b) = sin(a) cos(b) + cos(a) sin(b)
+        f += amp * (np.sin(a)[:, None] * np.cos(b)[None, :] + np.cos(a)[:, None] * np.sin(b)[None, :])
     for _ in range(4):
         nv = int(g_poly.integers(3, 7))
         vy = g_poly.uniform(0.0, rows, size=nv)
@@ -81,7 +103,7 @@ def synthetic_image(rows: int, cols: int, seed: int = 0, noise_sigma: float = 0.
         order = np.argsort(np.arctan2(vy - cy, vx - cx))
         verts = np.stack([vy[order], vx[order]], axis=1)
         val = g_poly.uniform(-64.0, 64.0)
-        f += val * _fill_polygon(rows, cols, verts)
+        f += val * _fill_polygon(r1 - r0, c1 - c0, verts, r0, c0)
     clean = np.clip(f, 0.0, 255.0)
     observed = clean
     if noise_sigma > 0.0:

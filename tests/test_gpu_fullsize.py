@@ -1,0 +1,169 @@
+"""GPU parity at the full workload sizes, in the launch configurations the
+benchmark times (FP32: persistent batched launch replayed from its graph;
+FP64: the plain one-wavefront-per-window launch).
+
+The oracle computes every window of the 512x512 frame, the 256x256 centre
+crop of the larger frames (their windows read the full measurements), and
+random samples plus border windows elsewhere. Bars: FP64 <= 1e-9 max-abs;
+FP32 <= 0.05 max-abs and <= 0.01 dB PSNR delta, no diverged selection
+sequence against the oracle on the same float32 input.
+"""
+import numpy as np
+import pytest
+
+from synth import batch_cases, make_case
+from tests.oracle_runs import centre_blocks, run_blocks, sample_blocks
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-9
+FP32_TOL = 0.05
+B = 4
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_02646_amd import ljsde
+    ljsde.lib()
+    return ljsde
+
+
+def _canon(k, W=32):
+    s, r = divmod(int(k), W)
+    return min(s * W + r, ((-s) % W) * W + (-r) % W)
+
+
+def _psnr(a, b):
+    return 10 * np.log10(255.0 ** 2 / np.mean((a - b) ** 2))
+
+
+def _gather(out, blocks):
+    return {(bi, bj): out[B * bi:B * bi + B, B * bj:B * bj + B] for bi, bj in blocks}
+
+
+def _fp32_batched(L, y32, tile, iters):
+    pid = L.plan(tile, iters=iters)
+    y = torch.from_numpy(y32).to("cuda:0")
+    out = torch.empty((2 * y32.shape[0], 2 * y32.shape[1]), dtype=torch.float32, device="cuda:0")
+    L.reconstruct_batch([(y, pid, out)])
+    L.reconstruct_batch([(y, pid, out)])         # graph replay
+    o = out.cpu().numpy().astype(np.float64)
+    return pid, y, o
+
+
+def _fp64_plain(L, y64, tile, iters):
+    pid = L.plan(tile, iters=iters, fp64=True)
+    o = L.reconstruct(torch.from_numpy(y64).to("cuda:0"), pid).cpu().numpy()
+    L.release(pid)
+    return o
+
+
+def _check_fp32(L, pid, y, o32, ref, clean, iters, label):
+    blocks = sorted(ref)
+    err = max(float(np.max(np.abs(o32[B * i:B * i + B, B * j:B * j + B] - ref[(i, j)][0]))) for i, j in blocks)
+    got = np.concatenate([o32[B * i:B * i + B, B * j:B * j + B].ravel() for i, j in blocks])
+    exp = np.concatenate([ref[(i, j)][0].ravel() for i, j in blocks])
+    cln = np.concatenate([clean[B * i:B * i + B, B * j:B * j + B].ravel() for i, j in blocks])
+    dpsnr = abs(_psnr(got, cln) - _psnr(exp, cln))
+    _, sel = L.reconstruct_diag(y, pid)
+    sel = sel.cpu().numpy()
+    nbj = o32.shape[1] // B
+    div = np.mean([not np.array_equal(sel[i * nbj + j], ref[(i, j)][1]) for i, j in blocks])
+    print(f"{label}: FP32 {len(blocks)} windows, max-abs {err:.3e}, PSNR delta {dpsnr:.2e} dB, "
+          f"diverged {div:.5f}", flush=True)
+    assert err <= FP32_TOL
+    assert dpsnr <= 0.01
+    assert div == 0.0
+
+
+def _check_fp64(o64, ref, label):
+    err = max(float(np.max(np.abs(o64[B * i:B * i + B, B * j:B * j + B] - ref[(i, j)][0]))) for i, j in ref)
+    print(f"{label}: FP64 {len(ref)} windows, max-abs {err:.3e}", flush=True)
+    assert err <= FP64_TOL
+
+
+def test_frame512_whole(L):
+    """512x512 frame, random 4x4-sensor tile, 100 iterations (the benchmark workload)."""
+    c = make_case(512, 512, 4, seed=0)
+    y32 = c["y"].astype(np.float32)
+    blocks = [(i, j) for i in range(128) for j in range(128)]
+    ref32 = run_blocks(y32.astype(np.float64), c["tile"], blocks, iters=100)
+    pid, y, o32 = _fp32_batched(L, y32, c["tile"], 100)
+    _check_fp32(L, pid, y, o32, ref32, c["clean"], 100, "frame512")
+    L.release(pid)
+    sample = sample_blocks(128, 128, 400, seed=1)
+    ref64 = run_blocks(c["y"], c["tile"], sample, iters=100)
+    _check_fp64(_fp64_plain(L, c["y"], c["tile"], 100), ref64, "frame512")
+
+
+def test_frame2048_noisy_crop(L):
+    """2048x2048 frame with N(0, 2^2) noise, random 8x8-sensor tile, 250 iterations."""
+    c = make_case(2048, 2048, 8, seed=0, noise=2.0)
+    y32 = c["y"].astype(np.float32)
+    crop = centre_blocks(512, 512, 256)
+    ref32 = run_blocks(y32.astype(np.float64), c["tile"], crop, iters=250)
+    pid, y, o32 = _fp32_batched(L, y32, c["tile"], 250)
+    _check_fp32(L, pid, y, o32, ref32, c["clean"], 250, "frame2048 crop")
+    L.release(pid)
+    sample = sample_blocks(512, 512, 150, seed=2)
+    ref64 = run_blocks(c["y"], c["tile"], sample, iters=250)
+    _check_fp64(_fp64_plain(L, c["y"], c["tile"], 250), ref64, "frame2048")
+
+
+def test_frame8192_many_classes_crop(L):
+    """8192x8192 frame, random 16x16-sensor tile (64 interior classes, 256 with
+    the border ones), 250 iterations."""
+    c = make_case(8192, 8192, 16, seed=0)
+    y32 = c["y"].astype(np.float32)
+    crop = centre_blocks(2048, 2048, 256)
+    ref32 = run_blocks(y32.astype(np.float64), c["tile"], crop, iters=250)
+    pid, y, o32 = _fp32_batched(L, y32, c["tile"], 250)
+    _check_fp32(L, pid, y, o32, ref32, c["clean"], 250, "frame8192 crop")
+    L.release(pid)
+    del y
+    sample = sample_blocks(2048, 2048, 100, seed=3)
+    ref64 = run_blocks(c["y"], c["tile"], sample, iters=250)
+    _check_fp64(_fp64_plain(L, c["y"], c["tile"], 250), ref64, "frame8192")
+
+
+def test_paper_shape_1200(L):
+    """The paper's frame shape: 1200x1200, recurrent pattern of period 32 px."""
+    c = make_case(1200, 1200, 16, seed=0)
+    y32 = c["y"].astype(np.float32)
+    sample = sample_blocks(300, 300, 600, seed=4)
+    ref32 = run_blocks(y32.astype(np.float64), c["tile"], sample, iters=100)
+    pid, y, o32 = _fp32_batched(L, y32, c["tile"], 100)
+    _check_fp32(L, pid, y, o32, ref32, c["clean"], 100, "paper 1200")
+    L.release(pid)
+    ref64 = run_blocks(c["y"], c["tile"], sample[:200], iters=100)
+    _check_fp64(_fp64_plain(L, c["y"], c["tile"], 100), ref64, "paper 1200")
+
+
+def test_uneven_batch_64_images(L):
+    """64 images of uneven size, each with its own pattern of period 2, 4 or 8,
+    in one persistent graph-captured launch; 100 iterations."""
+    cases = batch_cases(64, seed=0)
+    items = []
+    for k, c in enumerate(cases):
+        y = torch.from_numpy(c["y"].astype(np.float32)).to("cuda:0")
+        pid = L.plan(c["tile"], iters=100)
+        out = torch.empty((2 * y.shape[0], 2 * y.shape[1]), dtype=torch.float32, device="cuda:0")
+        items.append((y, pid, out))
+    L.reconstruct_batch(items)
+    L.reconstruct_batch(items)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for k, (c, (y, pid, out)) in enumerate(zip(cases, items)):
+        nbr, nbc = out.shape[0] // B, out.shape[1] // B
+        sample = sample_blocks(nbr, nbc, 24, seed=10 + k)
+        ref = run_blocks(c["y"].astype(np.float32).astype(np.float64), c["tile"], sample, iters=100, procs=8)
+        o = out.cpu().numpy().astype(np.float64)
+        err = max(float(np.max(np.abs(o[B * i:B * i + B, B * j:B * j + B] - ref[(i, j)][0]))) for i, j in sample)
+        worst = max(worst, err)
+        assert err <= FP32_TOL, (k, err)
+    print(f"uneven batch: 64 images, worst sampled max-abs {worst:.3e}", flush=True)
+    for _, pid, _ in items:
+        L.release(pid)

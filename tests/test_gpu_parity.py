@@ -1,9 +1,12 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
 
 Bars (fixed by the project goal): FP64 mode <= 1e-9 max-abs; FP32 mode
-<= 0.05 grey levels max-abs and <= 0.01 dB PSNR delta. Selection sequences
-are compared modulo conjugation (an exact tie between conjugate partners
-whenever the residual is real; either choice gives the same real output).
+<= 0.05 grey levels max-abs and <= 0.01 dB PSNR delta. FP32 plans consume
+float32 measurements, so their oracle runs on those same values (rounded to
+float32, then computed in FP64). Selection sequences must be equal: ties
+(metrics within a relative 1e-10) go to the lowest frequency index on both
+sides. The all-FP32 variant decides in FP32 and is held to the output bars
+only.
 """
 import numpy as np
 import pytest
@@ -55,8 +58,10 @@ CASES = {
 def _case(name):
     rows, cols, pattern, W, B, iters, rho, gamma, q_ones, seed = CASES[name]
     c = make_case(rows, cols, pattern, seed=seed)
-    ref, tr = O.reconstruct(c["y"], c["tile"], W=W, B=B, iters=iters, rho=rho, gamma=gamma, form="RL",
-                            q_mode="ones" if q_ones else "fsr", traces=True)
+    kw = dict(W=W, B=B, iters=iters, rho=rho, gamma=gamma, form="RL", q_mode="ones" if q_ones else "fsr")
+    ref, tr = O.reconstruct(c["y"], c["tile"], traces=True, **kw)
+    c["y32"] = c["y"].astype(np.float32)
+    c["ref32"], c["tr32"] = O.reconstruct(c["y32"].astype(np.float64), c["tile"], traces=True, **kw)
     return c, ref, tr, dict(window=W, block=B, iters=iters, rho=rho, gamma=gamma, q_ones=q_ones)
 
 
@@ -82,47 +87,47 @@ def test_fp64_matches_oracle(L, name):
     W = kw["window"]
     nbj = out.shape[1] // kw["block"]
     for w in range(sel.shape[0]):
-        picks = tr[divmod(w, nbj)].picks
-        assert [_canon(k, W) for k in sel[w]] == [_canon(k, W) for k in picks], w
+        assert list(sel[w]) == tr[divmod(w, nbj)].picks, w
     L.release(pid)
 
 
+@pytest.mark.parametrize("state_fp32", [False, True], ids=["fp64state", "fp32state"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_fp32_matches_oracle(L, name):
+def test_fp32_matches_oracle(L, name, state_fp32):
     c, ref, tr, kw = _cached(name)
-    pid = L.plan(c["tile"], **kw)
-    out = L.reconstruct(_dev(c["y"], np.float32), pid).cpu().numpy().astype(np.float64)
-    err = np.max(np.abs(out - ref))
-    dpsnr = abs(_psnr(out, c["clean"]) - _psnr(ref, c["clean"]))
-    print(f"{name}: FP32 max-abs {err:.3e}, PSNR delta {dpsnr:.2e} dB")
+    ref32 = c["ref32"]
+    pid = L.plan(c["tile"], state_fp32=state_fp32, **kw)
+    out, sel = L.reconstruct_diag(_dev(c["y32"], np.float32), pid)
+    out_b = L.reconstruct(_dev(c["y32"], np.float32), pid)          # batched persistent path
+    assert torch.equal(out, out_b)
+    out = out.cpu().numpy().astype(np.float64)
+    sel = sel.cpu().numpy()
+    err = np.max(np.abs(out - ref32))
+    dpsnr = abs(_psnr(out, c["clean"]) - _psnr(ref32, c["clean"]))
+    W = kw["window"]
+    nbj = out.shape[1] // kw["block"]
+    div = np.mean([list(sel[w]) != c["tr32"][divmod(w, nbj)].picks for w in range(sel.shape[0])])
+    print(f"{name}: FP32 max-abs {err:.3e}, PSNR delta {dpsnr:.2e} dB, diverged windows {div:.4f}")
     assert err <= FP32_TOL
     assert dpsnr <= 0.01
+    if not state_fp32:
+        assert div == 0.0
     L.release(pid)
 
 
-def test_fp32_diag_path_matches_batched_path(L):
-    c, ref, tr, kw = _cached("w32b4_ragged")
-    pid = L.plan(c["tile"], **kw)
-    y = _dev(c["y"], np.float32)
-    a = L.reconstruct(y, pid)
-    b, sel = L.reconstruct_diag(y, pid)
-    torch.cuda.synchronize()
-    assert torch.equal(a, b)
-    L.release(pid)
-
-
-def test_batch_equals_single_and_graph_replays(L):
+@pytest.mark.parametrize("state_fp32", [False, True], ids=["fp64state", "fp32state"])
+def test_batch_equals_single_and_graph_replays(L, state_fp32):
     """Uneven images, different patterns and periods, one persistent launch
-    replayed from its graph; every replay equals the eager single-image run."""
+    replayed from its graph; every replay equals the single-image run."""
     shapes = [(40, 48, 2), (64, 40, 4), (24, 24, 8), (48, 72, 4)]
     items, singles = [], []
     for k, (r, cc, per) in enumerate(shapes):
         case = make_case(r, cc, per, seed=20 + k)
-        pid = L.plan(case["tile"], iters=20)
+        pid = L.plan(case["tile"], iters=20, state_fp32=state_fp32)
         y = _dev(case["y"], np.float32)
         out = torch.empty((r, cc), dtype=torch.float32, device="cuda:0")
         items.append((y, pid, out))
-        singles.append(L.reconstruct(y, pid).clone())
+        singles.append(L.reconstruct_diag(y, pid)[0].clone())
     for rep in range(4):
         for _, _, out in items:
             out.fill_(float("nan"))
