@@ -96,9 +96,9 @@ struct Plan {
     double rho = 0, gamma = 0, tau = 0;
     unsigned flags = 0;
     ClassLayout lay{};
-    std::vector<double> w, ew, dft, q;  // class-independent FP64 tables
+    std::vector<double> w, ew, dft, q, H;  // class-independent FP64 tables
     int device = -1;
-    double *d_consts = nullptr;         // w | ew | dft
+    double *d_consts = nullptr;         // w | ew | dft | H
     std::map<std::pair<int, int>, std::unique_ptr<SizeSet>> sizes;
     bool fp64() const { return (flags & LJSDE_FP64) != 0; }
 };
@@ -148,6 +148,23 @@ void build_constants(Plan &p) {
         p.dft[2 * k] = std::cos(a);
         p.dft[2 * k + 1] = std::sin(a);
     }
+    // H_o(sigma, rho) = sum over the three transparent quadrants (a, b) of
+    // e^{i theta (a sigma + b rho)} = box response - opaque quadrant's term
+    p.H.resize((size_t)W * W * 8);
+    for (int sg = 0; sg < W; ++sg)
+        for (int rh = 0; rh < W; ++rh) {
+            const double eur = p.ew[2 * sg], eui = p.ew[2 * sg + 1];
+            const double evr = p.ew[2 * rh], evi = p.ew[2 * rh + 1];
+            const int uv = (sg + rh) % W;
+            const double hbr = (1 + eur) * (1 + evr) - eui * evi;
+            const double hbi = (1 + eur) * evi + eui * (1 + evr);
+            const double Hr[4] = {hbr - 1.0, hbr - evr, hbr - eur, hbr - p.ew[2 * uv]};
+            const double Hi[4] = {hbi, hbi - evi, hbi - eui, hbi - p.ew[2 * uv + 1]};
+            for (int o = 0; o < 4; ++o) {
+                p.H[((size_t)(sg * W + rh) * 4 + o) * 2] = Hr[o];
+                p.H[((size_t)(sg * W + rh) * 4 + o) * 2 + 1] = Hi[o];
+            }
+        }
     p.q.resize(W * W);
     const double qmax = std::sqrt(2.0) * W / 2.0;
     for (int s = 0; s < W; ++s)
@@ -246,16 +263,10 @@ void build_class(const Plan &p, const SizeSet &s, int cls, unsigned char *dst, d
     float *qd32 = (float *)(dst + p.lay.offQD32);
     for (int sg = 0; sg < W; ++sg)
         for (int rh = 0; rh < W; ++rh) {
-            const double eur = p.ew[2 * sg], eui = p.ew[2 * sg + 1];
-            const double evr = p.ew[2 * rh], evi = p.ew[2 * rh + 1];
-            const int uv = (sg + rh) % W;
-            const double hbr = (1 + eur) * (1 + evr) - eui * evi;
-            const double hbi = (1 + eur) * evi + eui * (1 + evr);
-            const double Hr[4] = {hbr - 1.0, hbr - evr, hbr - eur, hbr - p.ew[2 * uv]};
-            const double Hi[4] = {hbi, hbi - evi, hbi - eui, hbi - p.ew[2 * uv + 1]};
-            double D = 0;
-            for (int o = 0; o < 4; ++o) D += (Hr[o] * Hr[o] + Hi[o] * Hi[o]) * mass[o];
             const int f = sg * W + rh;
+            const double *H = &p.H[(size_t)f * 8];
+            double D = 0;
+            for (int o = 0; o < 4; ++o) D += (H[2 * o] * H[2 * o] + H[2 * o + 1] * H[2 * o + 1]) * mass[o];
             Dout[f] = D;
             const bool pos = D > 0;
             qd[f] = pos ? p.q[f] / D : 0.0;
@@ -335,6 +346,7 @@ int ensure_device(Plan &p, SizeSet &s) {
         c.insert(c.end(), p.w.begin(), p.w.end());
         c.insert(c.end(), p.ew.begin(), p.ew.end());
         c.insert(c.end(), p.dft.begin(), p.dft.end());
+        c.insert(c.end(), p.H.begin(), p.H.end());
         void *d = nullptr;
         st = dev_alloc(&d, c.size() * sizeof(double));
         if (st) return st;
@@ -393,6 +405,7 @@ KParams make_params(const Plan &p) {
     k.c.w = p.d_consts;
     k.c.ew = p.d_consts + p.w.size();
     k.c.dft = p.d_consts + p.w.size() + p.ew.size();
+    k.c.H = p.d_consts + p.w.size() + p.ew.size() + p.dft.size();
     k.lay = p.lay;
     return k;
 }

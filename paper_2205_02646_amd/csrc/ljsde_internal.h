@@ -11,6 +11,8 @@ struct DevConsts {
     const double *w;    // [Ws*Ws] spatial weights w_m = rho^d_m (eq. (8))
     const double *ew;   // [W][2]  exp(+i 2 pi k / W), k < W
     const double *dft;  // [Ws][2] exp(-i 2 pi k / Ws), k < Ws
+    const double *H;    // [W*W][4][2] H_o(sigma, rho): response of the L-shaped pixel of
+                        // orientation o to the basis function (sigma, rho)
 };
 
 // Byte offsets inside one class block of the device table.

@@ -115,8 +115,9 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
         }
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
-            ldsS[((ip * WS + lam) * 4 + o) * 2] = acc[o].re;
-            ldsS[((ip * WS + lam) * 4 + o) * 2 + 1] = acc[o].im;
+            // stage order [o][ip][l]: consecutive lanes touch consecutive entries
+            ldsS[((o * WS + ip) * WS + lam) * 2] = acc[o].re;
+            ldsS[((o * WS + ip) * WS + lam) * 2 + 1] = acc[o].im;
         }
     }
     wave_lds_fence();
@@ -133,8 +134,8 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
             const T twr = (T)p.c.dft[2 * k], twi = (T)p.c.dft[2 * k + 1];
 #pragma unroll
             for (int o = 0; o < 4; ++o) {
-                const T ar = ldsS[((ip * WS + lam) * 4 + o) * 2];
-                const T ai = ldsS[((ip * WS + lam) * 4 + o) * 2 + 1];
+                const T ar = ldsS[((o * WS + ip) * WS + lam) * 2];
+                const T ai = ldsS[((o * WS + ip) * WS + lam) * 2 + 1];
                 P[t][o].re += ar * twr - ai * twi;
                 P[t][o].im += ar * twi + ai * twr;
             }
@@ -143,7 +144,8 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
     wave_lds_fence();
 
     // ---- class spectra S_o into LDS (FP64 table -> working precision) ------
-    for (int e = lane; e < NPOS * 8; e += 64) ldsS[e] = (T)S64[e];
+    // table order [pos][o][re, im] -> LDS order [o][pos][re, im] (bank-conflict-free reads)
+    for (int e = lane; e < NPOS * 8; e += 64) ldsS[((((e >> 1) & 3) * NPOS) + (e >> 3)) * 2 + (e & 1)] = (T)S64[e];
 
     // ---- per-lane constants -------------------------------------------------
     T qd[QPL][4];
@@ -185,10 +187,10 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
             if (nu > 0) {
                 // subtract the shifted weighted-mask spectra of the last pick
                 const int pos = ((kap - u) & (WS - 1)) * WS + ((lam - v) & (WS - 1));
-                const T *s = ldsS + pos * 8;
+                const T *s = ldsS + pos * 2;
 #pragma unroll
                 for (int o = 0; o < 4; ++o) {
-                    const T sr = s[2 * o], si = s[2 * o + 1];
+                    const T sr = s[o * NPOS * 2], si = s[o * NPOS * 2 + 1];
                     P[t][o].re -= g4[o].re * sr - g4[o].im * si;
                     P[t][o].im -= g4[o].re * si + g4[o].im * sr;
                 }
@@ -233,15 +235,14 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
         u = idx / W;
         v = idx % W;
 
-        // L-pixel responses of the selected basis function, FP64
-        const double eur = p.c.ew[2 * u], eui = p.c.ew[2 * u + 1];
-        const double evr = p.c.ew[2 * v], evi = p.c.ew[2 * v + 1];
-        const int uv = (u + v) & (W - 1);
-        const double euvr = p.c.ew[2 * uv], euvi = p.c.ew[2 * uv + 1];
-        const double hbr = (1.0 + eur) * (1.0 + evr) - eui * evi;
-        const double hbi = (1.0 + eur) * evi + eui * (1.0 + evr);
-        double Hr[4] = {hbr - 1.0, hbr - evr, hbr - eur, hbr - euvr};
-        double Hi[4] = {hbi, hbi - evi, hbi - eui, hbi - euvi};
+        // L-pixel responses of the selected basis function (FP64 table)
+        const double *Hp = p.c.H + (size_t)idx * 8;  // uniform index: scalar loads
+        double Hr[4], Hi[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            Hr[o] = Hp[2 * o];
+            Hi[o] = Hp[2 * o + 1];
+        }
 
         // R_uv in FP64 from the owner lane's state
         const int ku = u & (WS - 1), lv = v & (WS - 1);

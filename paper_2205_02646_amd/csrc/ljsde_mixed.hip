@@ -240,14 +240,14 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         u = idx / W;
         v = idx % W;
 
-        // L-pixel responses H_o(u, v) of the selected basis function
-        const double eur = ew[2 * u], eui = ew[2 * u + 1];
-        const double evr = ew[2 * v], evi = ew[2 * v + 1];
-        const int uv = (u + v) & (W - 1);
-        const double hbr = (1.0 + eur) * (1.0 + evr) - eui * evi;
-        const double hbi = (1.0 + eur) * evi + eui * (1.0 + evr);
-        const double Hr[4] = {hbr - 1.0, hbr - evr, hbr - eur, hbr - ew[2 * uv]};
-        const double Hi[4] = {hbi, hbi - evi, hbi - eui, hbi - ew[2 * uv + 1]};
+        // L-pixel responses H_o(u, v) of the selected basis function (FP64 table)
+        const double *Hp = p.c.H + (size_t)idx * 8;  // uniform index: scalar loads
+        double Hr[4], Hi[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            Hr[o] = Hp[2 * o];
+            Hi[o] = Hp[2 * o + 1];
+        }
 
         // R_uv in FP64 from the owner lane
         const int ku = u & (WS - 1), lv = v & (WS - 1);
