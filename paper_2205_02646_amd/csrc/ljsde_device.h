@@ -87,6 +87,60 @@ __device__ __forceinline__ void tie_merge(T &best, int &idx, T ob, int oi, T eps
     }
 }
 
+typedef double v4f64 __attribute__((ext_vector_type(4)));
+
+// Orientation-masked 16-point 2-D DFT of one window on FP64 MFMA
+// (v_mfma_f64_16x16x4f64), for all four orientations:
+//     P_o(k, l) = sum_{i, j} X(i, j) [code(i, j) = o] e^{-2 pi i (i k + j l) / 16}
+// as T = X_o G, P_o = G T with G(a, b) = e^{-2 pi i a b / 16} (symmetric).
+// MFMA 16x16x4 operands: lane L supplies A[L % 16][4c + L / 16] and
+// B[4c + L / 16][L % 16] for K-chunk c; the result holds D[L / 16 + 4r][L % 16]
+// in register r. The first product therefore leaves in register c exactly the
+// B operand the second one needs for chunk c, and the second leaves lane L
+// with P_o(L / 16 + 4t, L % 16) in register t: the positions this lane owns.
+// X is w * y in LDS ([i][j], absent pixels 0), Cd the codes, dft the table of
+// e^{-2 pi i k / 16}. Needs the whole wavefront active.
+template <typename XT>
+__device__ __forceinline__ void dft16_mfma(const XT *X, const signed char *Cd, const double *dft,
+                                           double Pre[4][4], double Pim[4][4]) {
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, q = lane >> 4;
+    double x[4], gr[4], gi[4];
+    int cd[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int j = 4 * c + q;
+        x[c] = (double)X[r16 * 16 + j];
+        cd[c] = Cd[r16 * 16 + j];
+        const int k = (j * r16) & 15;
+        gr[c] = dft[2 * k];
+        gi[c] = dft[2 * k + 1];
+    }
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        v4f64 tr = {0.0, 0.0, 0.0, 0.0}, ti = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double a = cd[c] == o ? x[c] : 0.0;
+            tr = __builtin_amdgcn_mfma_f64_16x16x4f64(a, gr[c], tr, 0, 0, 0);
+            ti = __builtin_amdgcn_mfma_f64_16x16x4f64(a, gi[c], ti, 0, 0, 0);
+        }
+        v4f64 pr = {0.0, 0.0, 0.0, 0.0}, pi = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            pr = __builtin_amdgcn_mfma_f64_16x16x4f64(gr[c], tr[c], pr, 0, 0, 0);
+            pr = __builtin_amdgcn_mfma_f64_16x16x4f64(-gi[c], ti[c], pr, 0, 0, 0);
+            pi = __builtin_amdgcn_mfma_f64_16x16x4f64(gr[c], ti[c], pi, 0, 0, 0);
+            pi = __builtin_amdgcn_mfma_f64_16x16x4f64(gi[c], tr[c], pi, 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            Pre[t][o] = pr[t];
+            Pim[t][o] = pi[t];
+        }
+    }
+}
+
 // median of three (the backend selects v_med3_u32)
 __device__ __forceinline__ unsigned umed3(unsigned a, unsigned b, unsigned c) {
     return max(min(a, b), min(max(a, b), c));

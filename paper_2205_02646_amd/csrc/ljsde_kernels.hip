@@ -52,8 +52,10 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
     constexpr int QPL = WS * WS / 64;
     constexpr int NPOS = WS * WS;
     const int lane = threadIdx.x & 63;
+    // lane L owns the positions k = L / WS + KSTEP t (t < QPL), l = L % WS
+    constexpr int KSTEP = 64 / WS;
     const int lam = lane % WS;
-    const int kap0 = (lane / WS) * QPL;
+    const int krow = lane / WS;
 
     const int cls = j.rowcls[bi] * j.ncolk + j.colcls[bj];
     const unsigned char *tb = j.tables + (size_t)cls * p.lay.stride;
@@ -93,51 +95,60 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
     e0 = wave_sum(e0);  // weighted residual energy of eq. (8) at iteration 0
     wave_lds_fence();
 
-    // ---- orientation-masked weighted DFT, rows then columns ---------------
-#pragma unroll 1
-    for (int s = 0; s < QPL; ++s) {
-        const int ip = kap0 + s;
-        C2<T> acc[4];
+    // ---- orientation-masked weighted DFT -----------------------------------
+    C2<T> P[QPL][4];
+    if constexpr (WS == 16) {
+        double Pre[4][4], Pim[4][4];
+        dft16_mfma<T>(ldsX, ldsC, p.c.dft, Pre, Pim);
 #pragma unroll
-        for (int o = 0; o < 4; ++o) acc[o] = {T(0), T(0)};
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int o = 0; o < 4; ++o) P[t][o] = {(T)Pre[t][o], (T)Pim[t][o]};
+    } else {
+        // rows, then columns (VALU)
+#pragma unroll 1
+        for (int s = 0; s < QPL; ++s) {
+            const int ip = krow + KSTEP * s;
+            C2<T> acc[4];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) acc[o] = {T(0), T(0)};
 #pragma unroll 2
-        for (int jp = 0; jp < WS; ++jp) {
-            const T x = ldsX[ip * WS + jp];
-            const int c = ldsC[ip * WS + jp];
-            const int k = (jp * lam) & (WS - 1);
-            const T twr = (T)p.c.dft[2 * k], twi = (T)p.c.dft[2 * k + 1];
+            for (int jp = 0; jp < WS; ++jp) {
+                const T x = ldsX[ip * WS + jp];
+                const int c = ldsC[ip * WS + jp];
+                const int k = (jp * lam) & (WS - 1);
+                const T twr = (T)p.c.dft[2 * k], twi = (T)p.c.dft[2 * k + 1];
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    const T xo = (c == o) ? x : T(0);
+                    acc[o].re += xo * twr;
+                    acc[o].im += xo * twi;
+                }
+            }
 #pragma unroll
             for (int o = 0; o < 4; ++o) {
-                const T xo = (c == o) ? x : T(0);
-                acc[o].re += xo * twr;
-                acc[o].im += xo * twi;
+                // stage order [o][ip][l]: consecutive lanes touch consecutive entries
+                ldsS[((o * WS + ip) * WS + lam) * 2] = acc[o].re;
+                ldsS[((o * WS + ip) * WS + lam) * 2 + 1] = acc[o].im;
             }
         }
+        wave_lds_fence();
 #pragma unroll
-        for (int o = 0; o < 4; ++o) {
-            // stage order [o][ip][l]: consecutive lanes touch consecutive entries
-            ldsS[((o * WS + ip) * WS + lam) * 2] = acc[o].re;
-            ldsS[((o * WS + ip) * WS + lam) * 2 + 1] = acc[o].im;
-        }
-    }
-    wave_lds_fence();
-
-    C2<T> P[QPL][4];
+        for (int t = 0; t < QPL; ++t) {
+            const int kap = krow + KSTEP * t;
 #pragma unroll
-    for (int t = 0; t < QPL; ++t) {
-        const int kap = kap0 + t;
-#pragma unroll
-        for (int o = 0; o < 4; ++o) P[t][o] = {T(0), T(0)};
+            for (int o = 0; o < 4; ++o) P[t][o] = {T(0), T(0)};
 #pragma unroll 2
-        for (int ip = 0; ip < WS; ++ip) {
-            const int k = (ip * kap) & (WS - 1);
-            const T twr = (T)p.c.dft[2 * k], twi = (T)p.c.dft[2 * k + 1];
+            for (int ip = 0; ip < WS; ++ip) {
+                const int k = (ip * kap) & (WS - 1);
+                const T twr = (T)p.c.dft[2 * k], twi = (T)p.c.dft[2 * k + 1];
 #pragma unroll
-            for (int o = 0; o < 4; ++o) {
-                const T ar = ldsS[((o * WS + ip) * WS + lam) * 2];
-                const T ai = ldsS[((o * WS + ip) * WS + lam) * 2 + 1];
-                P[t][o].re += ar * twr - ai * twi;
-                P[t][o].im += ar * twi + ai * twr;
+                for (int o = 0; o < 4; ++o) {
+                    const T ar = ldsS[((o * WS + ip) * WS + lam) * 2];
+                    const T ai = ldsS[((o * WS + ip) * WS + lam) * 2 + 1];
+                    P[t][o].re += ar * twr - ai * twi;
+                    P[t][o].im += ar * twi + ai * twr;
+                }
             }
         }
     }
@@ -152,7 +163,7 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
     C2<T> tk[QPL], tkl[QPL];
 #pragma unroll
     for (int t = 0; t < QPL; ++t) {
-        const int kap = kap0 + t;
+        const int kap = krow + KSTEP * t;
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -183,7 +194,7 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
         int code0 = 0, code1 = 0;
 #pragma unroll
         for (int t = 0; t < QPL; ++t) {
-            const int kap = kap0 + t;
+            const int kap = krow + KSTEP * t;
             if (nu > 0) {
                 // subtract the shifted weighted-mask spectra of the last pick
                 const int pos = ((kap - u) & (WS - 1)) * WS + ((lam - v) & (WS - 1));
@@ -224,8 +235,8 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
         }
         // a = 1 frequencies have higher indices than all a = 0 ones
         T best = best0;
-        int idx = (kap0 + (code0 >> 1)) * W + lam + WS * (code0 & 1);
-        tie_merge<T>(best, idx, best1, (kap0 + (code1 >> 1) + WS) * W + lam + WS * (code1 & 1), eps);
+        int idx = (krow + KSTEP * (code0 >> 1)) * W + lam + WS * (code0 & 1);
+        tie_merge<T>(best, idx, best1, (krow + KSTEP * (code1 >> 1) + WS) * W + lam + WS * (code1 & 1), eps);
         for (int o = 32; o > 0; o >>= 1) {
             const T ob = __shfl_xor(best, o);
             const int oid = __shfl_xor(idx, o);
@@ -246,8 +257,8 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
 
         // R_uv in FP64 from the owner lane's state
         const int ku = u & (WS - 1), lv = v & (WS - 1);
-        const int tu = ku % QPL;
-        const int owner = (ku / QPL) * WS + lv;
+        const int tu = ku / KSTEP;
+        const int owner = (ku % KSTEP) * WS + lv;
         C2<T> Pu[4];
 #pragma unroll
         for (int o = 0; o < 4; ++o) Pu[o] = P[0][o];
@@ -294,8 +305,16 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
     }
 }
 
+// occupancy targets: 2 wavefronts per SIMD in FP64 (state 64 VGPRs alone),
+// 3 with the FP32 state
+template <typename T>
+struct Occ {
+    static constexpr int waves = sizeof(T) == 8 ? 2 : 3;
+};
+
 template <typename T, int WS>
-__global__ __launch_bounds__(64) void plain_kernel(KParams p, KJob j) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Occ<T>::waves))) void plain_kernel(KParams p,
+                                                                                                        KJob j) {
     extern __shared__ char lds[];
     const long long w = blockIdx.x;
     const long long nwin = (long long)j.nbi * j.nbj;
@@ -308,7 +327,7 @@ __global__ void reset_counter_kernel(unsigned int *counter) {
 }
 
 template <typename T, int WS>
-__global__ __launch_bounds__(256) void persistent_kernel(KParams p, const KJob *__restrict__ jobs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void persistent_kernel(KParams p, const KJob *__restrict__ jobs,
                                                          int njobs, long long total,
                                                          unsigned int *counter, int chunk) {
     extern __shared__ char lds[];

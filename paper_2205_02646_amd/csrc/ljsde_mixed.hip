@@ -75,8 +75,10 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
     // opaque per window: stops lane-derived addressing from being hoisted out
     // of the persistent loop and kept live (in VGPRs) across all windows
     asm volatile("" : "+v"(lane));
+    // lane L owns the positions k = L / WS + KSTEP t (t < QPL), l = L % WS
+    constexpr int KSTEP = 64 / WS;
     const int lam = lane % WS;
-    const int kap0 = (lane / WS) * QPL;
+    const int krow = lane / WS;
     const double *dft = tab;           // [WS][2] exp(-2 pi i k / WS)
     const double *ew = tab + 2 * WS;   // [W][2]  exp(+2 pi i k / W)
 
@@ -115,39 +117,48 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
     e0 = uniform_f64(wave_sum(e0));
     wave_lds_fence();
 
-    // ---- FP64 orientation-masked DFT, one orientation at a time -----------
+    // ---- FP64 orientation-masked DFT of the window --------------------------
     C2<double> P[QPL][4];
+    if constexpr (WS == 16) {
+        double Pre[4][4], Pim[4][4];
+        dft16_mfma<double>(X, Cd, dft, Pre, Pim);
 #pragma unroll
-    for (int o = 0; o < 4; ++o) {  // unrolled: P must be indexed statically
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int o = 0; o < 4; ++o) P[t][o] = {Pre[t][o], Pim[t][o]};
+    } else {
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {  // unrolled: P must be indexed statically
 #pragma unroll 1
-        for (int s = 0; s < QPL; ++s) {
-            const int ip = kap0 + s;
-            C2<double> acc = {0.0, 0.0};
+            for (int s = 0; s < QPL; ++s) {
+                const int ip = krow + KSTEP * s;
+                C2<double> acc = {0.0, 0.0};
 #pragma unroll 4
-            for (int jp = 0; jp < WS; ++jp) {
-                const double x = (Cd[ip * WS + jp] == o) ? X[ip * WS + jp] : 0.0;
-                const int k = (jp * lam) & (WS - 1);
-                acc.re += x * dft[2 * k];
-                acc.im += x * dft[2 * k + 1];
+                for (int jp = 0; jp < WS; ++jp) {
+                    const double x = (Cd[ip * WS + jp] == o) ? X[ip * WS + jp] : 0.0;
+                    const int k = (jp * lam) & (WS - 1);
+                    acc.re += x * dft[2 * k];
+                    acc.im += x * dft[2 * k + 1];
+                }
+                stage[ip * WS + lam] = acc;
             }
-            stage[ip * WS + lam] = acc;
-        }
-        wave_lds_fence();
+            wave_lds_fence();
 #pragma unroll
-        for (int t = 0; t < QPL; ++t) {
-            const int kap = kap0 + t;
-            C2<double> acc = {0.0, 0.0};
+            for (int t = 0; t < QPL; ++t) {
+                const int kap = krow + KSTEP * t;
+                C2<double> acc = {0.0, 0.0};
 #pragma unroll 4
-            for (int ip = 0; ip < WS; ++ip) {
-                const C2<double> a = stage[ip * WS + lam];
-                const int k = (ip * kap) & (WS - 1);
-                const double tr = dft[2 * k], ti = dft[2 * k + 1];
-                acc.re += a.re * tr - a.im * ti;
-                acc.im += a.re * ti + a.im * tr;
+                for (int ip = 0; ip < WS; ++ip) {
+                    const C2<double> a = stage[ip * WS + lam];
+                    const int k = (ip * kap) & (WS - 1);
+                    const double tr = dft[2 * k], ti = dft[2 * k + 1];
+                    acc.re += a.re * tr - a.im * ti;
+                    acc.im += a.re * ti + a.im * tr;
+                }
+                P[t][o] = acc;
             }
-            P[t][o] = acc;
+            wave_lds_fence();
         }
-        wave_lds_fence();
     }
 
     const C2<float> tl = {(float)ew[2 * lam], (float)-ew[2 * lam + 1]};
@@ -165,7 +176,7 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         unsigned kb = 0u, ks = 0u;
 #pragma unroll
         for (int t = 0; t < QPL; ++t) {
-            const int kap = kap0 + t;
+            const int kap = krow + KSTEP * t;
             if (nu > 0) {
                 // eq. (17), factorised: subtract the shifted weighted-mask spectra
                 const int pos = ((kap - u) & (WS - 1)) * WS + ((lam - v) & (WS - 1));
@@ -203,14 +214,14 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
             const int L = __builtin_ctzll(hit);
             const int code = (int)(M & 15u);
             const int t = code >> 2, a = (code >> 1) & 1, b = code & 1;
-            idx = ((L / WS) * QPL + t + WS * a) * W + (L % WS) + WS * b;
+            idx = ((L / WS) + KSTEP * t + WS * a) * W + (L % WS) + WS * b;
         } else {
             // near tie: decide in FP64 from the FP64 state
             double b0 = -1.0, b1 = -1.0;
             int i0 = 0, i1 = 0;
 #pragma unroll
             for (int t = 0; t < QPL; ++t) {
-                const int kap = kap0 + t;
+                const int kap = krow + KSTEP * t;
                 const C2<double> dtk = {ew[2 * kap], -ew[2 * kap + 1]};
                 const C2<double> dtkl = {ew[2 * (kap + lam)], -ew[2 * (kap + lam) + 1]};
                 const C2<double> dtl = {ew[2 * lam], -ew[2 * lam + 1]};
@@ -251,8 +262,8 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
 
         // R_uv in FP64 from the owner lane
         const int ku = u & (WS - 1), lv = v & (WS - 1);
-        const int tu = ku % QPL;
-        const int owner = (ku / QPL) * WS + lv;
+        const int tu = ku / KSTEP;
+        const int owner = (ku % KSTEP) * WS + lv;
         double rr = 0.0, ri = 0.0;
 #pragma unroll
         for (int t = 0; t < QPL; ++t) {
@@ -316,7 +327,7 @@ __device__ __forceinline__ void stage_tables(const KParams &p, const KJob &j, in
     // q/D of the 4 frequencies (k + Ws a, l + Ws b) of each lane's positions
     for (int e = tid; e < QPL * 64 * 4; e += blockDim.x) {
         const int c = e & 3, ln = (e >> 2) & 63, t = e >> 8;
-        const int kap = (ln / WS) * QPL + t, lam = ln % WS;
+        const int kap = (ln / WS) + (64 / WS) * t, lam = ln % WS;
         qdl[e] = qD32[(kap + WS * (c >> 1)) * W + lam + WS * (c & 1)];
     }
     if (with_tab) {
@@ -327,7 +338,7 @@ __device__ __forceinline__ void stage_tables(const KParams &p, const KJob &j, in
         // e^{-i theta k} and e^{-i theta (k + l)} per lane position
         for (int e = threadIdx.x; e < QPL * 64; e += blockDim.x) {
             const int ln = e & 63, t = e >> 6;
-            const int kap = (ln / WS) * QPL + t, lam = ln % WS;
+            const int kap = (ln / WS) + (64 / WS) * t, lam = ln % WS;
             twl[e * 4 + 0] = (float)p.c.ew[2 * kap];
             twl[e * 4 + 1] = (float)-p.c.ew[2 * kap + 1];
             twl[e * 4 + 2] = (float)p.c.ew[2 * (kap + lam)];
@@ -338,7 +349,7 @@ __device__ __forceinline__ void stage_tables(const KParams &p, const KJob &j, in
 
 // One window per workgroup (used for selection diagnostics).
 template <int WS>
-__global__ __launch_bounds__(64) void mixed_window_kernel(KParams p, KJob j) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void mixed_window_kernel(KParams p, KJob j) {
     extern __shared__ __align__(16) char lds[];
     using L = MixedLds<WS>;
     const long long w = blockIdx.x;
