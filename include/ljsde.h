@@ -53,8 +53,10 @@ enum {
     LJSDE_FP32 = 2,           /* FP32 projections, metric and argmax search; FP64 loop state,
                                  tables, step and energy; an FP32 near tie (relative 1e-4) is
                                  re-decided in FP64. measurements/out are float */
-    LJSDE_DFT_SPLITBF16 = 4,  /* FP32 plans: window DFT on MFMA with 3-term split-BF16
-                                 products and FP32 accumulation */
+    LJSDE_DFT_SPLITBF16 = 4,  /* FP32 plans, W = 32: window DFT on MFMA with 3-term split-BF16
+                                 products and FP32 accumulation instead of FP64 MFMA (relative
+                                 error ~2^-16 in the initial state; selections can then
+                                 diverge from FP64 at near ties) */
     LJSDE_Q_ONES = 8,         /* frequency weight q = 1 (test mode) */
     LJSDE_STATE_FP32 = 16     /* FP32 plans: keep the loop state and its updates in FP32 too
                                  (no FP64 re-decision); greedy selections can then diverge

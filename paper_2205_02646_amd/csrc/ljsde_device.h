@@ -141,6 +141,99 @@ __device__ __forceinline__ void dft16_mfma(const XT *X, const signed char *Cd, c
     }
 }
 
+typedef __bf16 v8bf16 __attribute__((ext_vector_type(8)));
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+
+// Same DFT as dft16_mfma with 3-term split-BF16 products on
+// v_mfma_f32_16x16x32_bf16 and FP32 accumulation: x = x_h + x_l with
+// x_h = bf16(x), x_l = bf16(x - x_h), and x g ~ x_h g_h + x_l g_h + x_h g_l.
+// The K = 32 of the instruction holds two 16-terms: [X_h | X_l] [G_h; G_h]
+// gives X_h G_h + X_l G_h, [X_h | X_l] [G_l; 0] gives X_h G_l. Operands: lane L
+// supplies A[L % 16][8 (L / 16) + e] and B[8 (L / 16) + e][L % 16] (e < 8); the
+// result holds D[4 (L / 16) + r][L % 16], so the intermediate and the result
+// pass through `lds` (>= 2 x 256 floats, wavefront-private) to reach the
+// layout of the next step. Relative error ~2^-16.
+template <typename XT>
+__device__ __forceinline__ void dft16_splitbf16(const XT *X, const signed char *Cd, const double *dft,
+                                                float *lds, double Pre[4][4], double Pim[4][4]) {
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, q = lane >> 4;
+    const bool low = q >= 2;           // this lane feeds the second 16 of K
+    const int k0 = 8 * (q & 1);        // first row/column (mod 16) of its 8 elements
+    // G(k0 + e, r16) = G(r16, k0 + e): the B operand of the first product and
+    // the A operand of the second are the same values
+    v8bf16 GrHH, GrL0, GiHH, GiL0, nGiHH, nGiL0;
+    float xv[8];
+    int cd[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int k = ((k0 + e) * r16) & 15;
+        const float gr = (float)dft[2 * k], gi = (float)dft[2 * k + 1];
+        const __bf16 grh = (__bf16)gr, gih = (__bf16)gi;
+        const __bf16 grl = (__bf16)(gr - (float)grh), gil = (__bf16)(gi - (float)gih);
+        GrHH[e] = grh;
+        GiHH[e] = gih;
+        nGiHH[e] = (__bf16)(-(float)gih);
+        GrL0[e] = low ? (__bf16)0.0f : grl;
+        GiL0[e] = low ? (__bf16)0.0f : gil;
+        nGiL0[e] = low ? (__bf16)0.0f : (__bf16)(-(float)gil);
+        xv[e] = (float)X[r16 * 16 + k0 + e];
+        cd[e] = Cd[r16 * 16 + k0 + e];
+    }
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        v8bf16 A1;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float x = cd[e] == o ? xv[e] : 0.0f;
+            const __bf16 h = (__bf16)x;
+            A1[e] = low ? (__bf16)(x - (float)h) : h;
+        }
+        v4f32 tr = {0.f, 0.f, 0.f, 0.f}, ti = {0.f, 0.f, 0.f, 0.f};
+        tr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, GrHH, tr, 0, 0, 0);
+        tr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, GrL0, tr, 0, 0, 0);
+        ti = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, GiHH, ti, 0, 0, 0);
+        ti = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, GiL0, ti, 0, 0, 0);
+        wave_lds_fence();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {  // T[4q + r][r16], real plane then imaginary plane
+            lds[(4 * q + r) * 16 + r16] = tr[r];
+            lds[256 + (4 * q + r) * 16 + r16] = ti[r];
+        }
+        wave_lds_fence();
+        v8bf16 BTr, BTi;  // [T_h; T_l]
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float a = lds[(k0 + e) * 16 + r16], b = lds[256 + (k0 + e) * 16 + r16];
+            const __bf16 ah = (__bf16)a, bh = (__bf16)b;
+            BTr[e] = low ? (__bf16)(a - (float)ah) : ah;
+            BTi[e] = low ? (__bf16)(b - (float)bh) : bh;
+        }
+        v4f32 pr = {0.f, 0.f, 0.f, 0.f}, pi = {0.f, 0.f, 0.f, 0.f};
+        pr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(GrHH, BTr, pr, 0, 0, 0);
+        pr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(GrL0, BTr, pr, 0, 0, 0);
+        pr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nGiHH, BTi, pr, 0, 0, 0);
+        pr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nGiL0, BTi, pr, 0, 0, 0);
+        pi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(GrHH, BTi, pi, 0, 0, 0);
+        pi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(GrL0, BTi, pi, 0, 0, 0);
+        pi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(GiHH, BTr, pi, 0, 0, 0);
+        pi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(GiL0, BTr, pi, 0, 0, 0);
+        wave_lds_fence();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {  // P[4q + r][r16]
+            lds[(4 * q + r) * 16 + r16] = pr[r];
+            lds[256 + (4 * q + r) * 16 + r16] = pi[r];
+        }
+        wave_lds_fence();
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {  // this lane's positions (q + 4t, r16)
+            Pre[t][o] = (double)lds[(q + 4 * t) * 16 + r16];
+            Pim[t][o] = (double)lds[256 + (q + 4 * t) * 16 + r16];
+        }
+    }
+    wave_lds_fence();
+}
+
 // median of three (the backend selects v_med3_u32)
 __device__ __forceinline__ unsigned umed3(unsigned a, unsigned b, unsigned c) {
     return max(min(a, b), min(max(a, b), c));

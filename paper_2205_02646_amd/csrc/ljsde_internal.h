@@ -33,6 +33,7 @@ struct KParams {
     double gamma;  // gamma_odc
     double ecoef;  // 2 gamma - gamma^2
     double tau;    // energy floor (0 = off)
+    int dft_bf16;  // window DFT with split-BF16 MFMA products (FP32 plans)
     DevConsts c;
     ClassLayout lay;
 };

@@ -60,7 +60,7 @@ __device__ __forceinline__ void project4(const C2<T> P[4], C2<T> tl, C2<T> tk, C
     R[3] = {s1.re - s2.re, s1.im - s2.im};  // (1, 1)
 }
 
-template <int WS>
+template <int WS, bool BF16>
 __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJob &j, int bi, int bj,
                                                      long long win_local, char *wlds, const char *glds) {
     using LL = MixedLds<WS>;
@@ -121,7 +121,8 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
     C2<double> P[QPL][4];
     if constexpr (WS == 16) {
         double Pre[4][4], Pim[4][4];
-        dft16_mfma<double>(X, Cd, dft, Pre, Pim);
+        if constexpr (BF16) dft16_splitbf16<double>(X, Cd, dft, (float *)stage, Pre, Pim);
+        else dft16_mfma<double>(X, Cd, dft, Pre, Pim);
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -348,7 +349,7 @@ __device__ __forceinline__ void stage_tables(const KParams &p, const KJob &j, in
 }
 
 // One window per workgroup (used for selection diagnostics).
-template <int WS>
+template <int WS, bool BF16>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void mixed_window_kernel(KParams p, KJob j) {
     extern __shared__ __align__(16) char lds[];
     using L = MixedLds<WS>;
@@ -358,11 +359,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void mi
     const int bi = (int)(w / j.nbj), bj = (int)(w % j.nbj);
     stage_tables<WS>(p, j, j.rowcls[bi] * j.ncolk + j.colcls[bj], lds, true);
     __syncthreads();
-    process_window_mixed<WS>(p, j, bi, bj, w, lds + L::shared_bytes, lds);
+    process_window_mixed<WS, BF16>(p, j, bi, bj, w, lds + L::shared_bytes, lds);
 }
 
 // Persistent: workgroups pull groups of up to NW same-class windows.
-template <int WS, int NW>
+template <int WS, int NW, bool BF16>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void mixed_persistent_kernel(KParams p, const KJob *__restrict__ jobs,
                                                                    const WinGroup *__restrict__ groups,
                                                                    int ngroups, unsigned int *counter) {
@@ -388,7 +389,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
         __syncthreads();
         if (wave < gcount) {
             const int lw = __builtin_amdgcn_readfirstlane(groups[gi].win[wave]);
-            process_window_mixed<WS>(p, J, lw / J.nbj, lw % J.nbj, lw, wl, lds);
+            process_window_mixed<WS, BF16>(p, J, lw / J.nbj, lw % J.nbj, lw, wl, lds);
         }
         __syncthreads();
     }
@@ -400,38 +401,44 @@ int launch_mixed_window(const KParams &p, const KJob &job, int ws, void *stream)
     const long long nwin = (long long)job.nbi * job.nbj;
     if (nwin <= 0) return 0;
     const size_t lds = mixed_lds_bytes(ws, 1);
-    if (ws == 16)
-        mixed_window_kernel<16><<<dim3((unsigned)nwin), dim3(64), lds, (hipStream_t)stream>>>(p, job);
+    const dim3 grid((unsigned)nwin), block(64);
+    if (ws == 16 && p.dft_bf16)
+        mixed_window_kernel<16, true><<<grid, block, lds, (hipStream_t)stream>>>(p, job);
+    else if (ws == 16)
+        mixed_window_kernel<16, false><<<grid, block, lds, (hipStream_t)stream>>>(p, job);
     else
-        mixed_window_kernel<8><<<dim3((unsigned)nwin), dim3(64), lds, (hipStream_t)stream>>>(p, job);
+        mixed_window_kernel<8, false><<<grid, block, lds, (hipStream_t)stream>>>(p, job);
     return (int)hipGetLastError();
 }
 
-template <int WS, int NW>
+template <int WS, int NW, bool BF16>
 static int launch_mp(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, int ngroups,
                      unsigned int *counter, int grid, void *stream) {
     const size_t lds = MixedLds<WS>::bytes(NW);
-    mixed_persistent_kernel<WS, NW><<<dim3(grid), dim3(64 * NW), lds, (hipStream_t)stream>>>(p, d_jobs, d_groups,
-                                                                                            ngroups, counter);
+    mixed_persistent_kernel<WS, NW, BF16><<<dim3(grid), dim3(64 * NW), lds, (hipStream_t)stream>>>(
+        p, d_jobs, d_groups, ngroups, counter);
     return (int)hipGetLastError();
+}
+
+template <int WS, bool BF16>
+static int launch_mp_nw(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, int ngroups,
+                        unsigned int *counter, int nw, int grid, void *stream) {
+    if (nw == 1) return launch_mp<WS, 1, BF16>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
+    if (nw == 2) return launch_mp<WS, 2, BF16>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
+    return launch_mp<WS, 4, BF16>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
 }
 
 int launch_mixed_persistent(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, int ngroups,
                             unsigned int *counter, int ws, int nw, int grid, void *stream) {
-    if (ws == 16) {
-        if (nw == 1) return launch_mp<16, 1>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
-        if (nw == 2) return launch_mp<16, 2>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
-        return launch_mp<16, 4>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
-    }
-    if (nw == 1) return launch_mp<8, 1>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
-    if (nw == 2) return launch_mp<8, 2>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
-    return launch_mp<8, 4>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
+    if (ws == 16 && p.dft_bf16) return launch_mp_nw<16, true>(p, d_jobs, d_groups, ngroups, counter, nw, grid, stream);
+    if (ws == 16) return launch_mp_nw<16, false>(p, d_jobs, d_groups, ngroups, counter, nw, grid, stream);
+    return launch_mp_nw<8, false>(p, d_jobs, d_groups, ngroups, counter, nw, grid, stream);
 }
 
 template <int WS, int NW>
 static int occ_mp(int *blocks) {
-    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, mixed_persistent_kernel<WS, NW>, 64 * NW,
-                                                             MixedLds<WS>::bytes(NW));
+    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, mixed_persistent_kernel<WS, NW, false>,
+                                                             64 * NW, MixedLds<WS>::bytes(NW));
 }
 
 int mixed_blocks_per_cu(int ws, int nw, int *blocks) {

@@ -52,6 +52,9 @@ TILE = random_pattern(4, 4, seed=0)
     (dict(window=64), ljsde.EUNSUPPORTED),      # valid for the method, no kernel
     (dict(window=32, block=12), ljsde.EUNSUPPORTED),
     (dict(fp64=True, splitbf16=True), ljsde.EINVAL),
+    (dict(fp64=True, state_fp32=True), ljsde.EINVAL),
+    (dict(splitbf16=True, state_fp32=True), ljsde.EUNSUPPORTED),
+    (dict(splitbf16=True, window=16), ljsde.EUNSUPPORTED),
 ])
 def test_plan_validation(kwargs, code):
     with pytest.raises(ljsde.LjsdeError) as e:

@@ -167,3 +167,29 @@ def test_uneven_batch_64_images(L):
     print(f"uneven batch: 64 images, worst sampled max-abs {worst:.3e}", flush=True)
     for _, pid, _ in items:
         L.release(pid)
+
+
+@pytest.mark.parametrize("variant", ["splitbf16", "state_fp32"])
+def test_frame512_brief_precision_recipes_hold_the_psnr_bar(L, variant):
+    """The brief's precision recipes (split-BF16 window DFT; FP32 loop state)
+    keep the PSNR delta within 0.01 dB on the whole 512x512 frame, but their
+    selections diverge from FP64 at near ties in some windows, so they are
+    options, not the default (their max-abs is reported, not bounded)."""
+    c = make_case(512, 512, 4, seed=0)
+    y32 = c["y"].astype(np.float32)
+    blocks = [(i, j) for i in range(128) for j in range(128)]
+    ref = run_blocks(y32.astype(np.float64), c["tile"], blocks, iters=100)
+    pid = L.plan(c["tile"], iters=100, **{variant: True})
+    y = torch.from_numpy(y32).to("cuda:0")
+    out = torch.empty((512, 512), dtype=torch.float32, device="cuda:0")
+    L.reconstruct_batch([(y, pid, out)])
+    o = out.cpu().numpy().astype(np.float64)
+    exp = np.zeros_like(o)
+    for (i, j), (blk, _, _) in ref.items():
+        exp[B * i:B * i + B, B * j:B * j + B] = blk
+    err = np.abs(o - exp).reshape(128, 4, 128, 4).max(axis=(1, 3))
+    dpsnr = abs(_psnr(o, c["clean"]) - _psnr(exp, c["clean"]))
+    print(f"{variant}: max-abs {err.max():.3e}, windows above 0.05: {np.mean(err > 0.05):.5f}, "
+          f"PSNR delta {dpsnr:.2e} dB", flush=True)
+    assert dpsnr <= 0.01
+    L.release(pid)

@@ -189,3 +189,27 @@ def test_energy_floor_stops_early_like_a_shorter_oracle_run(L):
         blk = np.s_[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4]
         assert np.max(np.abs(out[blk] - ref[blk])) <= FP64_TOL
     L.release(pid)
+
+
+def test_splitbf16_dft_accuracy_after_one_iteration(L):
+    """The split-BF16 window DFT has a relative error of ~2^-16: after one
+    iteration (one pick and step per window) the outputs match the oracle to
+    ~1e-4 of their scale wherever the pick agrees, and the pick agrees in all
+    but rare near ties."""
+    c = make_case(128, 128, 4, seed=41)
+    y32 = c["y"].astype(np.float32)
+    ref, tr = O.reconstruct(y32.astype(np.float64), c["tile"], iters=1, form="RL", traces=True)
+    pid = L.plan(c["tile"], iters=1, splitbf16=True)
+    out, sel = L.reconstruct_diag(_dev(y32, np.float32), pid)
+    out = out.cpu().numpy().astype(np.float64)
+    sel = sel.cpu().numpy()
+    nbj = 128 // 4
+    same = [w for w in range(sel.shape[0]) if sel[w, 0] == tr[divmod(w, nbj)].picks[0]]
+    assert len(same) >= 0.99 * sel.shape[0]
+    scale = np.max(np.abs(ref))
+    err = max(np.max(np.abs(out[4 * (w // nbj):4 * (w // nbj) + 4, 4 * (w % nbj):4 * (w % nbj) + 4]
+                             - ref[4 * (w // nbj):4 * (w // nbj) + 4, 4 * (w % nbj):4 * (w % nbj) + 4]))
+              for w in same)
+    print(f"split-BF16, 1 iteration: {len(same)}/{sel.shape[0]} equal picks, max-abs {err:.3e} (scale {scale:.1f})")
+    assert err <= 2e-4 * scale
+    L.release(pid)
