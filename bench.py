@@ -1,14 +1,20 @@
 """Benchmark of the RL-JSDE hot path on one MI355X.
 
-Workload: a 512x512 synthetic grey image (sinusoids + polygons on a 128
-base), three-quarter-sampled through a random recurrent 4x4-sensor-pixel
-opaque-quadrant tile; window 32, block 4, 100 iterations, rho 0.7, gamma 0.5.
-A step is one reconstruction of the whole frame by the FP32 batched path
-(persistent kernel replayed from its HIP graph). The plain FP64 GPU path is
-timed on the same input beside it, and the FP64 CPU oracle on a bounded
-sample of windows.
+Default workload (``--workload frame512``): a 512x512 synthetic grey image
+(sinusoids + polygons on a 128 base) three-quarter-sampled through a random
+recurrent 4x4-sensor-pixel opaque-quadrant tile; window 32, block 4, 100
+iterations, rho 0.7, gamma 0.5. A step is one reconstruction of the workload
+by the FP32 batched path (persistent kernel replayed from its HIP graph). The
+plain FP64 GPU path is timed on the same input beside it, and the FP64 CPU
+oracle on a bounded sample of windows.
 
-Prints one JSON line (see the README for the fields).
+Other workloads (``--workload``): frame2048 (2048x2048 + N(0, 2^2) noise,
+8x8-sensor tile, 250 iterations), frame8192 (8192x8192, 16x16-sensor tile,
+250 iterations), paper1200 (1200x1200, 16x16-sensor tile, 100 iterations),
+batch64 (64 images of uneven size, each with its own pattern of period 2, 4
+or 8, 100 iterations, one batched launch).
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -24,14 +30,26 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from synth import make_case  # noqa: E402
+from synth import batch_cases, make_case  # noqa: E402
 
-W, B, ITERS, RHO, GAMMA = 32, 4, 100, 0.7, 0.5
-ROWS = COLS = 512
-PERIOD = 4
+W, B, RHO, GAMMA = 32, 4, 0.7, 0.5
 FLOPS_PER_FREQ_ITER = 30          # factorised form: projection 18, metric 4, update 8
 PEAK_FP32_VALU = 157.3e12         # MI355X FP32 vector peak (packed), FLOP/s
-KERNEL_SOURCES = ["paper_2205_02646_amd/csrc/ljsde_kernels.hip", "paper_2205_02646_amd/csrc/ljsde_internal.h"]
+KERNEL_SOURCES = ["paper_2205_02646_amd/csrc/ljsde_mixed.hip", "paper_2205_02646_amd/csrc/ljsde_device.h",
+                  "paper_2205_02646_amd/csrc/ljsde_internal.h"]
+
+WORKLOADS = {
+    "frame512": dict(kind="frame", rows=512, cols=512, period=4, iters=100, noise=0.0,
+                     desc="512x512 frame, recurrent 4x4-sensor pattern"),
+    "frame2048": dict(kind="frame", rows=2048, cols=2048, period=8, iters=250, noise=2.0,
+                      desc="2048x2048 frame + N(0,2^2) noise, recurrent 8x8-sensor pattern"),
+    "frame8192": dict(kind="frame", rows=8192, cols=8192, period=16, iters=250, noise=0.0,
+                      desc="8192x8192 frame, recurrent 16x16-sensor pattern (64 interior / 256 classes)"),
+    "paper1200": dict(kind="frame", rows=1200, cols=1200, period=16, iters=100, noise=0.0,
+                      desc="1200x1200 frame, recurrent 16x16-sensor pattern (period 32 px)"),
+    "batch64": dict(kind="batch", n=64, iters=100,
+                    desc="64 images of uneven size, own patterns of period 2/4/8"),
+}
 
 
 def kernel_hash() -> str:
@@ -42,57 +60,58 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(nwin: int):
+def load_traffic(workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "persistent_f32_512x512_traffic.json")
+    path = os.path.join(ROOT, "profiles", "mixed_persistent_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
-        rec = json.load(fh)
-    if rec.get("kernel_hash") != kernel_hash():
+        rec = json.load(fh).get(workload)
+    if not rec or rec.get("kernel_hash") != kernel_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
 
 
 def _oracle_worker(args):
-    y, tile, blocks = args
-    os.environ["OMP_NUM_THREADS"] = "1"
+    y, tile, blocks, iters = args
     from oracle import ljsde_oracle as O
     try:
         from threadpoolctl import threadpool_limits
-        ctx = threadpool_limits(1)
+        threadpool_limits(1)
     except Exception:  # pragma: no cover
-        ctx = None
-    out = O.reconstruct(y, tile, W=W, B=B, iters=ITERS, rho=RHO, gamma=GAMMA, form="RL", blocks=blocks)
-    if ctx is not None:
-        ctx.unregister()
+        pass
+    out = O.reconstruct(y, tile, W=W, B=B, iters=iters, rho=RHO, gamma=GAMMA, form="RL", blocks=blocks)
     return [(bi, bj, out[B * bi:B * bi + B, B * bj:B * bj + B]) for bi, bj in blocks]
 
 
-def cpu_baseline(y, tile, n_windows: int, seed: int = 1):
+def cpu_baseline(y, tile, iters: int, n_windows: int, seed: int = 1, label: str = ""):
     """Time the FP64 oracle (RL-JSDE form) on a random sample of windows over
     the host cores; returns (record, {block: output})."""
     import multiprocessing as mp
     rng = np.random.default_rng(seed)
     nbi, nbj = 2 * y.shape[0] // B, 2 * y.shape[1] // B
+    n_windows = min(n_windows, nbi * nbj)
     flat = rng.choice(nbi * nbj, size=n_windows, replace=False)
     blocks = [divmod(int(f), nbj) for f in np.sort(flat)]
     cores = min(os.cpu_count() or 1, 16)
-    # group by block row so that workers share per-class precompute
     chunks = [blocks[k::cores] for k in range(cores)]
-    ctx = mp.get_context("fork")
     t0 = time.perf_counter()
-    with ctx.Pool(cores) as pool:
-        parts = pool.map(_oracle_worker, [(y, tile, c) for c in chunks if c])
+    with mp.get_context("fork").Pool(cores) as pool:
+        parts = pool.map(_oracle_worker, [(y, tile, c, iters) for c in chunks if c])
     dt = time.perf_counter() - t0
     res = {(bi, bj): blk for part in parts for bi, bj, blk in part}
-    mps = n_windows * B * B / dt / 1e6
-    rec = {"value": mps, "unit": "MP/s", "cores": cores, "kind": "oracle",
-           "sample": f"{n_windows} random windows ({n_windows * B * B} px) of the 512x512 frame, "
-                     f"RL-JSDE form (dense per-class B, C, D), {dt:.1f} s wall on {cores} processes "
+    rec = {"value": n_windows * B * B / dt / 1e6, "unit": "MP/s", "cores": cores, "kind": "oracle",
+           "sample": f"{n_windows} random windows ({n_windows * B * B} px) of the {label}, RL-JSDE form "
+                     f"(dense per-class B, C, D), {iters} iterations, {dt:.1f} s wall on {cores} processes "
                      f"with 1 BLAS thread each"}
     return rec, res
+
+
+def build_inputs(wl: dict):
+    if wl["kind"] == "frame":
+        return [make_case(wl["rows"], wl["cols"], wl["period"], seed=0, noise=wl["noise"])]
+    return batch_cases(wl["n"], seed=0)
 
 
 def main():
@@ -100,8 +119,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="frame512", choices=sorted(WORKLOADS))
     ap.add_argument("--oracle-windows", type=int, default=512)
     ap.add_argument("--no-oracle", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 path")
     ap.add_argument("--profile-copy", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -110,34 +131,41 @@ def main():
               "(windows are independent; see the sharding notes in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
-    case = make_case(ROWS, COLS, PERIOD, seed=0)
-    y64, tile, clean = case["y"], case["tile"], case["clean"]
+    wl = WORKLOADS[args.workload]
+    iters = wl["iters"]
+    cases = build_inputs(wl)
+    y32h = [c["y"].astype(np.float32) for c in cases]
 
-    # FP32 plans consume float32 measurements: the oracle runs on those values
-    y32h = y64.astype(np.float32)
+    # FP32 plans consume float32 measurements: their oracle runs on those values
     oracle_rec, oracle_blocks, oracle64_blocks = (None, {}, {})
     if not args.no_oracle:
-        oracle_rec, oracle_blocks = cpu_baseline(y32h.astype(np.float64), tile, args.oracle_windows)
-        _, oracle64_blocks = cpu_baseline(y64, tile, 128, seed=2)
+        label = wl["desc"].split(",")[0] if wl["kind"] == "frame" else "first image of the batch"
+        oracle_rec, oracle_blocks = cpu_baseline(y32h[0].astype(np.float64), cases[0]["tile"], iters,
+                                                 args.oracle_windows, label=label)
+        _, oracle64_blocks = cpu_baseline(cases[0]["y"], cases[0]["tile"], iters, 128, seed=2)
 
     import torch
     from paper_2205_02646_amd import ljsde
 
     dev = torch.device("cuda:0")
-    y32 = torch.from_numpy(y32h).to(dev)
-    y64d = torch.from_numpy(y64).to(dev)
-    p32 = ljsde.plan(tile, window=W, block=B, iters=ITERS, rho=RHO, gamma=GAMMA)
-    p64 = ljsde.plan(tile, window=W, block=B, iters=ITERS, rho=RHO, gamma=GAMMA, fp64=True)
-    out32 = torch.empty((ROWS, COLS), dtype=torch.float32, device=dev)
-    out64 = torch.empty((ROWS, COLS), dtype=torch.float64, device=dev)
-    jobs = [(y32, p32, out32)]
     stream = torch.cuda.current_stream()
+    jobs, runs64 = [], []
+    for c, y in zip(cases, y32h):
+        rows, cols = 2 * y.shape[0], 2 * y.shape[1]
+        p32 = ljsde.plan(c["tile"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA)
+        jobs.append((torch.from_numpy(y).to(dev), p32,
+                     torch.empty((rows, cols), dtype=torch.float32, device=dev)))
+        if not args.no_fp64:
+            p64 = ljsde.plan(c["tile"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA, fp64=True)
+            runs64.append((torch.from_numpy(c["y"]).to(dev), p64,
+                           torch.empty((rows, cols), dtype=torch.float64, device=dev)))
 
     def step32():
         ljsde.reconstruct_batch(jobs, stream=stream)
 
     def step64():
-        ljsde.reconstruct(y64d, p64, out=out64, stream=stream)
+        for y, pid, out in runs64:
+            ljsde.reconstruct(y, pid, out=out, stream=stream)
 
     def timed(fn, steps, warmup):
         for _ in range(warmup):
@@ -166,34 +194,42 @@ def main():
         del a, b
 
     ms32 = timed(step32, args.steps, args.warmup)
-    ms64 = timed(step64, max(3, args.steps // 4), 1)
+    ms64 = timed(step64, max(2, min(args.steps // 4, 5)), 1) if runs64 else None
     ljsde.synchronize(stream)
 
-    o32 = out32.cpu().numpy().astype(np.float64)
-    o64 = out64.cpu().numpy()
-    mp = ROWS * COLS / 1e6
-    nwin = (ROWS // B) * (COLS // B)
+    px = sum(2 * y.shape[0] * 2 * y.shape[1] for y in y32h)
+    nwin = sum((2 * y.shape[0] // B) * (2 * y.shape[1] // B) for y in y32h)
+    mp = px / 1e6
+
+    o32 = jobs[0][2].cpu().numpy().astype(np.float64)
+    clean = cases[0]["clean"]
 
     def psnr(a):
         return float(10 * np.log10(255.0 ** 2 / np.mean((a - clean) ** 2)))
 
-    quality = {"psnr_fp32_db": psnr(o32), "psnr_fp64_db": psnr(o64),
-               "psnr_delta_fp32_vs_fp64_db": abs(psnr(o32) - psnr(o64)),
-               "maxabs_fp32_vs_fp64": float(np.max(np.abs(o32 - o64)))}
+    quality = {"psnr_fp32_db_first_image": psnr(o32)}
+    if runs64:
+        o64 = runs64[0][2].cpu().numpy()
+        quality.update({"psnr_fp64_db_first_image": psnr(o64),
+                        "psnr_delta_fp32_vs_fp64_db": abs(psnr(o32) - psnr(o64)),
+                        "maxabs_fp32_vs_fp64": float(np.max(np.abs(o32 - o64))),
+                        "note": "FP32 runs on float32-rounded measurements, FP64 on the float64 ones"})
     if oracle_blocks:
         e32 = max(float(np.max(np.abs(o32[B * i:B * i + B, B * j:B * j + B] - blk)))
                   for (i, j), blk in oracle_blocks.items())
-        e64 = max(float(np.max(np.abs(o64[B * i:B * i + B, B * j:B * j + B] - blk)))
-                  for (i, j), blk in oracle64_blocks.items())
-        quality.update({"maxabs_fp32_vs_oracle_sample": e32, "oracle_sample_windows_fp32": len(oracle_blocks),
-                        "maxabs_fp64_vs_oracle_sample": e64, "oracle_sample_windows_fp64": len(oracle64_blocks)})
+        quality.update({"maxabs_fp32_vs_oracle_sample": e32, "oracle_sample_windows_fp32": len(oracle_blocks)})
+        if runs64:
+            e64 = max(float(np.max(np.abs(o64[B * i:B * i + B, B * j:B * j + B] - blk)))
+                      for (i, j), blk in oracle64_blocks.items())
+            quality.update({"maxabs_fp64_vs_oracle_sample": e64,
+                            "oracle_sample_windows_fp64": len(oracle64_blocks)})
 
-    flops = nwin * ITERS * W * W * FLOPS_PER_FREQ_ITER
+    flops = nwin * iters * W * W * FLOPS_PER_FREQ_ITER
     achieved = flops / (ms32 * 1e-3)
-    value = mp / (ms32 * 1e-3)
+    hbm_bytes = 4 * sum(y.size for y in y32h) + 4 * px      # float32 measurements in, float32 image out
     rec = {
         "metric": "reconstructed MP/s (FP32 batched vs FP64 plain, same GPU) at <=0.01 dB PSNR delta",
-        "value": value,
+        "value": mp / (ms32 * 1e-3),
         "unit": "MP/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -204,16 +240,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "RL-JSDE 512x512 frame, recurrent 4x4-sensor pattern, W=32 B=4, "
-                               "100 iterations, rho 0.7, gamma 0.5 (FP32 persistent batched launch)",
-                   "rows": ROWS, "cols": COLS, "pattern_period": PERIOD, "window": W, "block": B,
-                   "iters": ITERS, "windows": nwin},
-        "fp64_plain": {"value": mp / (ms64 * 1e-3), "unit": "MP/s", "ms_per_step": ms64},
-        "speedup_fp32_batched_vs_fp64_plain": ms64 / ms32,
+        "config": {"workload": f"RL-JSDE {wl['desc']}, W=32 B=4, {iters} iterations, rho 0.7, gamma 0.5 "
+                               "(FP32 persistent batched launch)",
+                   "name": args.workload, "images": len(cases), "megapixels": mp, "window": W, "block": B,
+                   "iters": iters, "windows": nwin},
+        "fp64_plain": ({"value": mp / (ms64 * 1e-3), "unit": "MP/s", "ms_per_step": ms64} if ms64 else None),
+        "speedup_fp32_batched_vs_fp64_plain": (ms64 / ms32 if ms64 else None),
         "quality": quality,
+        "hbm_algorithmic_gbps": hbm_bytes / (ms32 * 1e-3) / 1e9,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
-                     "traffic": load_traffic(nwin), "kernel_hash": kernel_hash()},
+                     "traffic": load_traffic(args.workload), "kernel_hash": kernel_hash()},
         "cpu_baseline": oracle_rec,
     }
     print(json.dumps(rec), flush=True)
