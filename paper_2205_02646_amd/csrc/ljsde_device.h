@@ -24,10 +24,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // DPP lane move inside rows of 16 lanes (quad_perm / mirror controls only:
-// every source lane is valid, so no lane keeps its old value).
+// every source lane is valid). The fill value 0 is the identity of an
+// unsigned max, which lets the move fold into a v_max_u32 with a DPP operand.
 template <int CTRL>
 __device__ __forceinline__ unsigned dpp_u32(unsigned v) {
-    return (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
 }
 
 constexpr int DPP_QUAD_XOR1 = 0xB1;   // quad_perm [1,0,3,2]
@@ -35,29 +36,16 @@ constexpr int DPP_QUAD_XOR2 = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int DPP_ROW_HALF_MIRROR = 0x141;
 constexpr int DPP_ROW_MIRROR = 0x140;
 
-// Top-two of unsigned keys over the wavefront. On return every lane holds
-// the largest key in `best` and the second largest in `second` (the second
-// may equal the first when two lanes hold equal keys).
-__device__ __forceinline__ void wave_top2_u32(unsigned &best, unsigned &second) {
-    unsigned b = best, s = second, bo, so;
-#define LJSDE_TOP2_STEP(CTRL)                     \
-    bo = dpp_u32<CTRL>(b);                        \
-    so = dpp_u32<CTRL>(s);                        \
-    s = max(max(s, so), min(b, bo));              \
-    b = max(b, bo);
-    LJSDE_TOP2_STEP(DPP_QUAD_XOR1)
-    LJSDE_TOP2_STEP(DPP_QUAD_XOR2)
-    LJSDE_TOP2_STEP(DPP_ROW_HALF_MIRROR)
-    LJSDE_TOP2_STEP(DPP_ROW_MIRROR)
-#undef LJSDE_TOP2_STEP
-    // four rows: combine their (best, second) pairs with scalar operations
-    const unsigned b0 = __builtin_amdgcn_readlane(b, 0), b1 = __builtin_amdgcn_readlane(b, 16);
-    const unsigned b2 = __builtin_amdgcn_readlane(b, 32), b3 = __builtin_amdgcn_readlane(b, 48);
-    const unsigned s0 = __builtin_amdgcn_readlane(s, 0), s1 = __builtin_amdgcn_readlane(s, 16);
-    const unsigned s2 = __builtin_amdgcn_readlane(s, 32), s3 = __builtin_amdgcn_readlane(s, 48);
-    const unsigned m01 = max(b0, b1), n01 = min(b0, b1), m23 = max(b2, b3), n23 = min(b2, b3);
-    best = max(m01, m23);
-    second = max(max(max(s0, s1), max(s2, s3)), max(min(m01, m23), max(n01, n23)));
+// Maximum of unsigned keys over the wavefront (a wave-uniform value): a
+// max-butterfly inside each row of 16 lanes, then the four row maxima.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+    v = max(v, dpp_u32<DPP_QUAD_XOR1>(v));
+    v = max(v, dpp_u32<DPP_QUAD_XOR2>(v));
+    v = max(v, dpp_u32<DPP_ROW_HALF_MIRROR>(v));
+    v = max(v, dpp_u32<DPP_ROW_MIRROR>(v));
+    const unsigned r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const unsigned r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    return max(max(r0, r1), max(r2, r3));
 }
 
 // Selection ties (eqs. (10)-(11)): metrics within a relative TIE_REL of the
@@ -238,6 +226,8 @@ __device__ __forceinline__ void dft16_splitbf16(const XT *X, const signed char *
 __device__ __forceinline__ unsigned umed3(unsigned a, unsigned b, unsigned c) {
     return max(min(a, b), min(max(a, b), c));
 }
+
+__device__ __forceinline__ unsigned umax3(unsigned a, unsigned b, unsigned c) { return max(max(a, b), c); }
 
 __device__ __forceinline__ double uniform_f64(double x) {
     const unsigned long long b = __double_as_longlong(x);

@@ -23,6 +23,10 @@ namespace ljsde {
 
 constexpr float NEAR_TIE = 1e-4f;
 
+// Constant address space view of read-only tables: wave-uniform indexing
+// then compiles to scalar loads.
+typedef const double __attribute__((address_space(4))) CDouble;
+
 template <int WS>
 struct MixedLds {
     static constexpr int NPOS = WS * WS;
@@ -163,32 +167,23 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
     }
 
     const C2<float> tl = {(float)ew[2 * lam], (float)-ew[2 * lam + 1]};
+    // the L-pixel response table, read with wave-uniform indices: scalar loads
+    const CDouble *Ht = (const CDouble *)p.c.H;
+    const CDouble *invDs = (const CDouble *)invD;
 
     const int BB = p.B * p.B;
     const int oi = lane / p.B, oj = lane % p.B;
     double outacc = 0.0;
     double E = e0;
-    double gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
-    int u = 0, v = 0;
     int nu_done = 0;
 
 #pragma unroll 1
     for (int nu = 0; nu < p.iters; ++nu) {
+        // eq. (11) in FP32 for the lane's frequencies; per-lane largest and
+        // second-largest key (metric bits, in-lane code in the low 4 bits)
         unsigned kb = 0u, ks = 0u;
 #pragma unroll
         for (int t = 0; t < QPL; ++t) {
-            const int kap = krow + KSTEP * t;
-            if (nu > 0) {
-                // eq. (17), factorised: subtract the shifted weighted-mask spectra
-                const int pos = ((kap - u) & (WS - 1)) * WS + ((lam - v) & (WS - 1));
-                const C2<double> *s = (const C2<double> *)Sl + pos;
-#pragma unroll
-                for (int o = 0; o < 4; ++o) {
-                    const C2<double> so = s[o * NPOS];
-                    P[t][o].re = fma(-gre[o], so.re, fma(gim[o], so.im, P[t][o].re));
-                    P[t][o].im = fma(-gre[o], so.im, fma(-gim[o], so.re, P[t][o].im));
-                }
-            }
             C2<float> Pf[4], R[4];
 #pragma unroll
             for (int o = 0; o < 4; ++o) Pf[o] = {(float)P[t][o].re, (float)P[t][o].im};
@@ -196,23 +191,28 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
             const float4 t4 = *(const float4 *)(twl + (t * 64 + lane) * 4);
             project4<float>(Pf, tl, C2<float>{t4.x, t4.y}, C2<float>{t4.z, t4.w}, R);
             const float qd[4] = {q4.x, q4.y, q4.z, q4.w};
+            unsigned key[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const float m = (R[c].re * R[c].re + R[c].im * R[c].im) * qd[c];
-                const unsigned key = (__float_as_uint(m) & ~15u) | (unsigned)(t * 4 + c);
-                ks = umed3(kb, ks, key);
-                kb = max(kb, key);
+                const float m = fmaf(R[c].re, R[c].re, R[c].im * R[c].im) * qd[c];
+                key[c] = (__float_as_uint(m) & ~15u) | (unsigned)(t * 4 + c);
             }
+            // top two of {kb, ks, a, b}: the second is max(ks, med3(kb, a, b))
+            ks = max(ks, umed3(kb, key[0], key[1]));
+            kb = umax3(kb, key[0], key[1]);
+            ks = max(ks, umed3(kb, key[2], key[3]));
+            kb = umax3(kb, key[2], key[3]);
             __builtin_amdgcn_sched_barrier(0);  // one position at a time: bounds register pressure
         }
-        unsigned M = kb, S2 = ks;
-        wave_top2_u32(M, S2);
-        const float fM = __uint_as_float(M & ~15u), fS = __uint_as_float(S2 & ~15u);
+        // The FP32 winner stands when no other key reaches (1 - NEAR_TIE) of
+        // it: exactly one lane's best and no lane's second are at or above it.
+        const unsigned M = wave_max_u32(kb);
+        const unsigned thr = __float_as_uint(__uint_as_float(M & ~15u) * (1.0f - NEAR_TIE));
+        const unsigned long long hi1 = __ballot(kb >= thr);
+        const unsigned long long hi2 = __ballot(ks >= thr);
         int idx;
-        if (fS < fM * (1.0f - NEAR_TIE)) {
-            // unique FP32 winner: its lane and in-lane code
-            const unsigned long long hit = __ballot(kb == M);
-            const int L = __builtin_ctzll(hit);
+        if (__popcll(hi1) == 1 && hi2 == 0ull) {
+            const int L = __builtin_ctzll(hi1);
             const int code = (int)(M & 15u);
             const int t = code >> 2, a = (code >> 1) & 1, b = code & 1;
             idx = ((L / WS) + KSTEP * t + WS * a) * W + (L % WS) + WS * b;
@@ -249,19 +249,17 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
             }
         }
         idx = __builtin_amdgcn_readfirstlane(idx);
-        u = idx / W;
-        v = idx % W;
+        const int u = idx / W, v = idx % W;
 
-        // L-pixel responses H_o(u, v) of the selected basis function (FP64 table)
-        const double *Hp = p.c.H + (size_t)idx * 8;  // uniform index: scalar loads
+        // L-pixel responses H_o(u, v) of the selected basis function (FP64)
         double Hr[4], Hi[4];
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
-            Hr[o] = Hp[2 * o];
-            Hi[o] = Hp[2 * o + 1];
+            Hr[o] = Ht[(size_t)idx * 8 + 2 * o];
+            Hi[o] = Ht[(size_t)idx * 8 + 2 * o + 1];
         }
 
-        // R_uv in FP64 from the owner lane
+        // R_uv = sum_o conj(H_o(u, v)) P_o in FP64, from the owner lane
         const int ku = u & (WS - 1), lv = v & (WS - 1);
         const int tu = ku / KSTEP;
         const int owner = (ku % KSTEP) * WS + lv;
@@ -271,8 +269,8 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
             if (tu == t) {
 #pragma unroll
                 for (int o = 0; o < 4; ++o) {
-                    rr += Hr[o] * P[t][o].re + Hi[o] * P[t][o].im;
-                    ri += Hr[o] * P[t][o].im - Hi[o] * P[t][o].re;
+                    rr = fma(Hr[o], P[t][o].re, fma(Hi[o], P[t][o].im, rr));
+                    ri = fma(Hr[o], P[t][o].im, fma(-Hi[o], P[t][o].re, ri));
                 }
             }
         }
@@ -280,14 +278,9 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         ri = readlane_f64(ri, owner);
 
         // eqs. (15)-(16) and the energy of eq. (8), FP64
-        const double id = invD[idx];
-        const double gr = p.gamma * rr * id, gi = p.gamma * ri * id;
+        const double id = invDs[idx];
+        const double gr = p.gamma * id * rr, gi = p.gamma * id * ri;
         E = uniform_f64(E - p.ecoef * (rr * rr + ri * ri) * id);
-#pragma unroll
-        for (int o = 0; o < 4; ++o) {
-            gre[o] = uniform_f64(gr * Hr[o] - gi * Hi[o]);
-            gim[o] = uniform_f64(gr * Hi[o] + gi * Hr[o]);
-        }
         // eq. (18) on the central block, pick by pick
         if (lane < BB) {
             const int ph = ((p.off + oi) * u + (p.off + oj) * v) & (W - 1);
@@ -296,6 +289,29 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         if (j.sel != nullptr && lane == 0) j.sel[win_local * p.iters + nu] = (int16_t)idx;
         nu_done = nu + 1;
         if (p.tau > 0.0 && E <= p.tau * e0) break;
+        if (nu + 1 == p.iters) break;
+
+        // eq. (17), factorised: P_o(k, l) -= g_o S_o(k - u, l - v) with
+        // g_o = gamma delta H_o(u, v) (wave-uniform, kept in vector registers
+        // for this phase only)
+        double gre[4], gim[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            gre[o] = fma(gr, Hr[o], -gi * Hi[o]);
+            gim[o] = fma(gr, Hi[o], gi * Hr[o]);
+        }
+#pragma unroll
+        for (int t = 0; t < QPL; ++t) {
+            const int kap = krow + KSTEP * t;
+            const int pos = ((kap - ku) & (WS - 1)) * WS + ((lam - lv) & (WS - 1));
+            const C2<double> *s = (const C2<double> *)Sl + pos;
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                const C2<double> so = s[o * NPOS];
+                P[t][o].re = fma(-gre[o], so.re, fma(gim[o], so.im, P[t][o].re));
+                P[t][o].im = fma(-gre[o], so.im, fma(-gim[o], so.re, P[t][o].im));
+            }
+        }
     }
     if (j.sel != nullptr)
         for (int nu = nu_done + lane; nu < p.iters; nu += 64) j.sel[win_local * p.iters + nu] = -1;
