@@ -447,9 +447,10 @@ struct BatchState {
     std::string tune_key;
     KJob *d_jobs = nullptr;
     WinGroup *d_groups = nullptr;
+    int *d_ranges = nullptr;            // XCD_RANGES + 1 offsets into d_groups
     int ngroups = 0;
     int groups_nw = 0;                  // group width the device list was built for
-    unsigned int *d_counter = nullptr;
+    unsigned int *d_counter = nullptr;  // COUNTERS work counters
     long long total = 0;
     KParams params{};
     int ws = 16;
@@ -463,6 +464,7 @@ struct BatchState {
         if (graph) (void)hipGraphDestroy(graph);
         if (d_jobs) (void)hipFree(d_jobs);
         if (d_groups) (void)hipFree(d_groups);
+        if (d_ranges) (void)hipFree(d_ranges);
         if (d_counter) (void)hipFree(d_counter);
     }
 };
@@ -539,31 +541,58 @@ int grid_for(const BatchState &b, const TuneChoice &c, int *grid) {
 // Work list of the FP64-state path: per job and class, the windows of that
 // class in row-major order, cut into groups of at most nw (the waves of one
 // workgroup share the class's spectra in LDS).
+// Work list of the persistent FP32 launch: groups of up to nw windows of one
+// class (they share the class tables staged in LDS). Windows are grouped
+// inside spatial tiles of the block grid, at least twice the class period on
+// each axis (the number of row / column keys bounds that period), so a group
+// is four nearby windows, and the tiles are listed in row-major order. The
+// list is cut into XCD_RANGES contiguous ranges of equal length.
 int build_groups(BatchState &b, int nw) {
     if (b.groups_nw == nw && b.d_groups) return LJSDE_OK;
     std::vector<WinGroup> groups;
     for (size_t ji = 0; ji < b.sizes.size(); ++ji) {
         const SizeSet &s = *b.sizes[ji];
         const int nck = (int)s.colkeys.size();
+        const int tr = std::min(s.nbi, std::max(16, 2 * (int)s.rowkeys.size()));
+        const int tc = std::min(s.nbj, std::max(16, 2 * (int)s.colkeys.size()));
         std::vector<std::vector<int>> by_class(s.n_classes());
-        for (int bi = 0; bi < s.nbi; ++bi)
-            for (int bj = 0; bj < s.nbj; ++bj) by_class[s.rowcls[bi] * nck + s.colcls[bj]].push_back(bi * s.nbj + bj);
-        for (const auto &ws : by_class)
-            for (size_t k = 0; k < ws.size(); k += nw) {
-                WinGroup g{};
-                g.job = (int)ji;
-                g.count = (int)std::min<size_t>(nw, ws.size() - k);
-                for (int w = 0; w < 4; ++w) g.win[w] = ws[k + std::min(w, g.count - 1)];
-                groups.push_back(g);
+        std::vector<int> used;  // classes met in the current tile, in first-seen order
+        for (int r0 = 0; r0 < s.nbi; r0 += tr)
+            for (int c0 = 0; c0 < s.nbj; c0 += tc) {
+                for (int bi = r0; bi < std::min(s.nbi, r0 + tr); ++bi)
+                    for (int bj = c0; bj < std::min(s.nbj, c0 + tc); ++bj) {
+                        const int cls = s.rowcls[bi] * nck + s.colcls[bj];
+                        if (by_class[cls].empty()) used.push_back(cls);
+                        by_class[cls].push_back(bi * s.nbj + bj);
+                    }
+                for (int cls : used) {
+                    const std::vector<int> &ws = by_class[cls];
+                    for (size_t k = 0; k < ws.size(); k += nw) {
+                        WinGroup g{};
+                        g.job = (int)ji;
+                        g.count = (int)std::min<size_t>(nw, ws.size() - k);
+                        for (int w = 0; w < 4; ++w) g.win[w] = ws[k + std::min(w, g.count - 1)];
+                        groups.push_back(g);
+                    }
+                    by_class[cls].clear();
+                }
+                used.clear();
             }
     }
+    int ranges[XCD_RANGES + 1];
+    for (int r = 0; r <= XCD_RANGES; ++r) ranges[r] = (int)((long long)groups.size() * r / XCD_RANGES);
     if (b.d_groups) {
         (void)hipFree(b.d_groups);
         b.d_groups = nullptr;
     }
     int st = dev_alloc((void **)&b.d_groups, sizeof(WinGroup) * std::max<size_t>(groups.size(), 1));
     if (st) return st;
+    if (!b.d_ranges) {
+        st = dev_alloc((void **)&b.d_ranges, sizeof(ranges));
+        if (st) return st;
+    }
     HIP_TRY(hipMemcpy(b.d_groups, groups.data(), sizeof(WinGroup) * groups.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b.d_ranges, ranges, sizeof(ranges), hipMemcpyHostToDevice));
     b.ngroups = (int)groups.size();
     b.groups_nw = nw;
     return LJSDE_OK;
@@ -625,7 +654,7 @@ int prepare_batch(const ljsde_job *jobs, int n, void *stream, BatchState **out) 
         if (sf32) b->choice = TuneChoice{1, 2};
         st = dev_alloc((void **)&b->d_jobs, sizeof(KJob) * n);
         if (st) return st;
-        st = dev_alloc((void **)&b->d_counter, sizeof(unsigned int));
+        st = dev_alloc((void **)&b->d_counter, sizeof(unsigned int) * COUNTERS);
         if (st) return st;
         load_tune_cache();
         auto t = g_tuned.find(b->tune_key);
@@ -663,7 +692,7 @@ int launch_batch_eager(BatchState &b, const TuneChoice &c, int grid, void *strea
         e = launch_persistent_f32(b.params, b.d_jobs, (int)b.host_jobs.size(), b.total, b.d_counter, b.ws,
                                   c.waves_per_block, c.chunk, grid, stream);
     else
-        e = launch_mixed_persistent(b.params, b.d_jobs, b.d_groups, b.ngroups, b.d_counter, b.ws,
+        e = launch_mixed_persistent(b.params, b.d_jobs, b.d_groups, b.d_ranges, b.d_counter, b.ws,
                                     c.waves_per_block, grid, stream);
     if (e) return fail(LJSDE_EHIP, "persistent launch: %s", hipGetErrorString((hipError_t)e));
     return LJSDE_OK;

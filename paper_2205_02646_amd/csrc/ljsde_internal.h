@@ -60,15 +60,21 @@ struct WinGroup {
 // Launch wrappers (ljsde_kernels.hip, ljsde_mixed.hip). Return a hipError_t value.
 int launch_plain_f64(const KParams &p, const KJob &job, int ws, void *stream);
 int launch_plain_f32(const KParams &p, const KJob &job, int ws, void *stream);
-int launch_reset_counter(unsigned int *counter, void *stream);
+// Zeroes the COUNTERS work counters of a batch (a fill kernel, so that the
+// reset can sit in a captured graph).
+constexpr int COUNTERS = 8;
+int launch_reset_counter(unsigned int *counters, void *stream);
 int launch_persistent_f32(const KParams &p, const KJob *d_jobs, int njobs, long long total_windows,
                           unsigned int *counter, int ws, int waves_per_block, int chunk,
                           int grid, void *stream);
 int persistent_blocks_per_cu(int ws, int waves_per_block, int *blocks);
 size_t lds_bytes_per_wave(int ws, bool fp64);
 int launch_mixed_window(const KParams &p, const KJob &job, int ws, void *stream);
-int launch_mixed_persistent(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, int ngroups,
-                            unsigned int *counter, int ws, int nw, int grid, void *stream);
+// Group ranges of the persistent FP32 launch: one per XCD of an MI355X.
+// range_begin holds XCD_RANGES + 1 offsets into the group list.
+constexpr int XCD_RANGES = COUNTERS;
+int launch_mixed_persistent(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, const int *range_begin,
+                            unsigned int *counters, int ws, int nw, int grid, void *stream);
 int mixed_blocks_per_cu(int ws, int nw, int *blocks);
 size_t mixed_lds_bytes(int ws, int nw);
 

@@ -322,8 +322,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Occ<T>::wave
     process_window<T, WS>(p, j, (int)(w / j.nbj), (int)(w % j.nbj), w, lds);
 }
 
-__global__ void reset_counter_kernel(unsigned int *counter) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+__global__ void reset_counter_kernel(unsigned int *counters) {
+    if (blockIdx.x == 0 && threadIdx.x < COUNTERS) counters[threadIdx.x] = 0u;
 }
 
 template <typename T, int WS>

@@ -26,6 +26,10 @@ constexpr float NEAR_TIE = 1e-4f;
 // Constant address space view of read-only tables: wave-uniform indexing
 // then compiles to scalar loads.
 typedef const double __attribute__((address_space(4))) CDouble;
+// Global address space view of the selection trace: its stores are then
+// global (vector-memory counter only) rather than flat, whose completion also
+// holds up the waits on LDS reads.
+typedef int16_t __attribute__((address_space(1))) GInt16;
 
 template <int WS>
 struct MixedLds {
@@ -182,13 +186,20 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         // eq. (11) in FP32 for the lane's frequencies; per-lane largest and
         // second-largest key (metric bits, in-lane code in the low 4 bits)
         unsigned kb = 0u, ks = 0u;
+        // per-lane q/D and twiddles of a position are read one position
+        // ahead, so their LDS latency overlaps the previous position's work
+        float4 q4n = *(const float4 *)(qdl + lane * 4);
+        float4 t4n = *(const float4 *)(twl + lane * 4);
 #pragma unroll
         for (int t = 0; t < QPL; ++t) {
+            const float4 q4 = q4n, t4 = t4n;
+            if (t + 1 < QPL) {
+                q4n = *(const float4 *)(qdl + ((t + 1) * 64 + lane) * 4);
+                t4n = *(const float4 *)(twl + ((t + 1) * 64 + lane) * 4);
+            }
             C2<float> Pf[4], R[4];
 #pragma unroll
             for (int o = 0; o < 4; ++o) Pf[o] = {(float)P[t][o].re, (float)P[t][o].im};
-            const float4 q4 = *(const float4 *)(qdl + (t * 64 + lane) * 4);
-            const float4 t4 = *(const float4 *)(twl + (t * 64 + lane) * 4);
             project4<float>(Pf, tl, C2<float>{t4.x, t4.y}, C2<float>{t4.z, t4.w}, R);
             const float qd[4] = {q4.x, q4.y, q4.z, q4.w};
             unsigned key[4];
@@ -281,35 +292,47 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         const double id = invDs[idx];
         const double gr = p.gamma * id * rr, gi = p.gamma * id * ri;
         E = uniform_f64(E - p.ecoef * (rr * rr + ri * ri) * id);
-        // eq. (18) on the central block, pick by pick
-        if (lane < BB) {
-            const int ph = ((p.off + oi) * u + (p.off + oj) * v) & (W - 1);
-            outacc += gr * ew[2 * ph] - gi * ew[2 * ph + 1];
-        }
-        if (j.sel != nullptr && lane == 0) j.sel[win_local * p.iters + nu] = (int16_t)idx;
-        nu_done = nu + 1;
-        if (p.tau > 0.0 && E <= p.tau * e0) break;
-        if (nu + 1 == p.iters) break;
-
-        // eq. (17), factorised: P_o(k, l) -= g_o S_o(k - u, l - v) with
-        // g_o = gamma delta H_o(u, v) (wave-uniform, kept in vector registers
-        // for this phase only)
+        // g_o = gamma delta H_o(u, v) of eq. (17) (wave-uniform, in vector
+        // registers for the update only); then the spectra of the first
+        // position of the update are read from LDS, so that their latency
+        // overlaps the back-transform and the stopping test
         double gre[4], gim[4];
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
             gre[o] = fma(gr, Hr[o], -gi * Hi[o]);
             gim[o] = fma(gr, Hi[o], gi * Hr[o]);
         }
+        const C2<double> *Sc = (const C2<double> *)Sl + ((lam - lv) & (WS - 1));
+        C2<double> sn[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) sn[o] = Sc[o * NPOS + ((krow - ku) & (WS - 1)) * WS];
+        __builtin_amdgcn_sched_barrier(0);
+        // eq. (18) on the central block, pick by pick
+        if (lane < BB) {
+            const int ph = ((p.off + oi) * u + (p.off + oj) * v) & (W - 1);
+            outacc += gr * ew[2 * ph] - gi * ew[2 * ph + 1];
+        }
+        if (j.sel != nullptr && lane == 0) ((GInt16 *)j.sel)[win_local * p.iters + nu] = (int16_t)idx;
+        nu_done = nu + 1;
+        if (p.tau > 0.0 && E <= p.tau * e0) break;
+        if (nu + 1 == p.iters) break;
+
+        // eq. (17), factorised: P_o(k, l) -= g_o S_o(k - u, l - v); the
+        // spectra of position t + 1 are read while position t is updated
 #pragma unroll
         for (int t = 0; t < QPL; ++t) {
-            const int kap = krow + KSTEP * t;
-            const int pos = ((kap - ku) & (WS - 1)) * WS + ((lam - lv) & (WS - 1));
-            const C2<double> *s = (const C2<double> *)Sl + pos;
+            C2<double> so[4];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) so[o] = sn[o];
+            if (t + 1 < QPL) {
+                const int row = (krow + KSTEP * (t + 1) - ku) & (WS - 1);
+#pragma unroll
+                for (int o = 0; o < 4; ++o) sn[o] = Sc[o * NPOS + row * WS];
+            }
 #pragma unroll
             for (int o = 0; o < 4; ++o) {
-                const C2<double> so = s[o * NPOS];
-                P[t][o].re = fma(-gre[o], so.re, fma(gim[o], so.im, P[t][o].re));
-                P[t][o].im = fma(-gre[o], so.im, fma(-gim[o], so.re, P[t][o].im));
+                P[t][o].re = fma(-gre[o], so[o].re, fma(gim[o], so[o].im, P[t][o].re));
+                P[t][o].im = fma(-gre[o], so[o].im, fma(-gim[o], so[o].re, P[t][o].im));
             }
         }
     }
@@ -378,24 +401,44 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void mi
     process_window_mixed<WS, BF16>(p, j, bi, bj, w, lds + L::shared_bytes, lds);
 }
 
-// Persistent: workgroups pull groups of up to NW same-class windows.
+// Persistent: workgroups pull groups of up to NW same-class windows. The
+// group list is ordered by spatial tile and cut into XCD_RANGES contiguous
+// ranges with one counter each; a workgroup drains the range of its own XCD
+// (workgroups are dealt to the XCDs round-robin) and then the others, so the
+// measurements and output lines of a tile stay in one XCD's L2. Every group
+// index is claimed exactly once whatever the actual placement.
 template <int WS, int NW, bool BF16>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void mixed_persistent_kernel(KParams p, const KJob *__restrict__ jobs,
                                                                    const WinGroup *__restrict__ groups,
-                                                                   int ngroups, unsigned int *counter) {
+                                                                   const int *__restrict__ range_begin,
+                                                                   unsigned int *counters) {
     extern __shared__ __align__(16) char lds[];
     using L = MixedLds<WS>;
     int *slot = (int *)(lds + L::offSlot);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     char *wl = lds + L::shared_bytes + (size_t)wave * L::wave_bytes;
+    const int home = (int)(blockIdx.x % XCD_RANGES);
+    int tried = 0;  // ranges found exhausted (thread 0 only)
     bool first = true;
     for (;;) {
-        if (threadIdx.x == 0) *slot = (int)atomicAdd(counter, 1u);
+        if (threadIdx.x == 0) {
+            int g = -1;
+            while (tried < XCD_RANGES) {
+                const int r = (home + tried) % XCD_RANGES;
+                const int k = (int)atomicAdd(counters + r, 1u);
+                if (k < range_begin[r + 1] - range_begin[r]) {
+                    g = range_begin[r] + k;
+                    break;
+                }
+                ++tried;
+            }
+            *slot = g;
+        }
         __syncthreads();
         // the group index is workgroup-uniform: keep it (and all that derives
         // from it) in scalar registers
         const int gi = __builtin_amdgcn_readfirstlane(*slot);
-        if (gi >= ngroups) break;
+        if (gi < 0) break;
         const int gjob = groups[gi].job, gcount = groups[gi].count;
         const KJob J = jobs[gjob];
         const int w0 = groups[gi].win[0];
@@ -428,27 +471,28 @@ int launch_mixed_window(const KParams &p, const KJob &job, int ws, void *stream)
 }
 
 template <int WS, int NW, bool BF16>
-static int launch_mp(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, int ngroups,
-                     unsigned int *counter, int grid, void *stream) {
+static int launch_mp(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, const int *range_begin,
+                     unsigned int *counters, int grid, void *stream) {
     const size_t lds = MixedLds<WS>::bytes(NW);
     mixed_persistent_kernel<WS, NW, BF16><<<dim3(grid), dim3(64 * NW), lds, (hipStream_t)stream>>>(
-        p, d_jobs, d_groups, ngroups, counter);
+        p, d_jobs, d_groups, range_begin, counters);
     return (int)hipGetLastError();
 }
 
 template <int WS, bool BF16>
-static int launch_mp_nw(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, int ngroups,
-                        unsigned int *counter, int nw, int grid, void *stream) {
-    if (nw == 1) return launch_mp<WS, 1, BF16>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
-    if (nw == 2) return launch_mp<WS, 2, BF16>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
-    return launch_mp<WS, 4, BF16>(p, d_jobs, d_groups, ngroups, counter, grid, stream);
+static int launch_mp_nw(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, const int *range_begin,
+                        unsigned int *counters, int nw, int grid, void *stream) {
+    if (nw == 1) return launch_mp<WS, 1, BF16>(p, d_jobs, d_groups, range_begin, counters, grid, stream);
+    if (nw == 2) return launch_mp<WS, 2, BF16>(p, d_jobs, d_groups, range_begin, counters, grid, stream);
+    return launch_mp<WS, 4, BF16>(p, d_jobs, d_groups, range_begin, counters, grid, stream);
 }
 
-int launch_mixed_persistent(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, int ngroups,
-                            unsigned int *counter, int ws, int nw, int grid, void *stream) {
-    if (ws == 16 && p.dft_bf16) return launch_mp_nw<16, true>(p, d_jobs, d_groups, ngroups, counter, nw, grid, stream);
-    if (ws == 16) return launch_mp_nw<16, false>(p, d_jobs, d_groups, ngroups, counter, nw, grid, stream);
-    return launch_mp_nw<8, false>(p, d_jobs, d_groups, ngroups, counter, nw, grid, stream);
+int launch_mixed_persistent(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, const int *range_begin,
+                            unsigned int *counters, int ws, int nw, int grid, void *stream) {
+    if (ws == 16 && p.dft_bf16)
+        return launch_mp_nw<16, true>(p, d_jobs, d_groups, range_begin, counters, nw, grid, stream);
+    if (ws == 16) return launch_mp_nw<16, false>(p, d_jobs, d_groups, range_begin, counters, nw, grid, stream);
+    return launch_mp_nw<8, false>(p, d_jobs, d_groups, range_begin, counters, nw, grid, stream);
 }
 
 template <int WS, int NW>
