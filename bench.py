@@ -144,6 +144,11 @@ def main():
                                                  args.oracle_windows, label=label)
         _, oracle64_blocks = cpu_baseline(cases[0]["y"], cases[0]["tile"], iters, 128, seed=2)
 
+    # the autotuner's choice is read back from its cache file for the report
+    import tempfile
+    tune_file = os.environ.setdefault("LJSDE_TUNE_CACHE",
+                                      os.path.join(tempfile.mkdtemp(prefix="ljsde_tune_"), "tune.json"))
+
     import torch
     from paper_2205_02646_amd import ljsde
 
@@ -180,8 +185,16 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps  # ms per step
 
-    # pick the launch variant (windows per workgroup) for this batch shape
+    # pick the launch variant (windows per workgroup, resident workgroups per
+    # CU) for this batch shape
     ljsde.autotune(jobs, stream=stream)
+    launch = None
+    try:
+        with open(tune_file) as fh:
+            launch = {k: {"waves_per_workgroup": v[0], "workgroups_per_cu_below_max": v[2]}
+                      for k, v in json.load(fh).items()}
+    except (OSError, ValueError, IndexError):
+        pass
 
     if args.profile_copy:
         # a plain device copy of known size (256 MiB read + 256 MiB written):
@@ -246,6 +259,7 @@ def main():
                    "iters": iters, "windows": nwin},
         "fp64_plain": ({"value": mp / (ms64 * 1e-3), "unit": "MP/s", "ms_per_step": ms64} if ms64 else None),
         "speedup_fp32_batched_vs_fp64_plain": (ms64 / ms32 if ms64 else None),
+        "launch": launch,
         "quality": quality,
         "hbm_algorithmic_gbps": hbm_bytes / (ms32 * 1e-3) / 1e9,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,

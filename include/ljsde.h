@@ -139,7 +139,8 @@ int ljsde_reconstruct_batch(const ljsde_job *jobs, int n_jobs, void *stream);
 
 /*
  * ljsde_autotune -- time the launch variants of the persistent kernel
- * (windows per workgroup, work-chunk size) on this batch and keep the
+ * (windows per workgroup, work-chunk size, resident workgroups per compute
+ * unit) on this batch and keep the
  * fastest for later batch calls of the same shape class. Results are cached
  * in memory and, if LJSDE_TUNE_CACHE names a file, in that JSON file.
  * Synchronises `stream`. Outputs of the batch are overwritten.

@@ -438,6 +438,7 @@ KJob make_job(const SizeSet &s, const void *y, void *out, int16_t *sel, long lon
 struct TuneChoice {
     int waves_per_block = 4;
     int chunk = 2;
+    int fewer_blocks = 0;  // resident workgroups per CU below the occupancy maximum
 };
 
 struct BatchState {
@@ -497,7 +498,7 @@ void load_tune_cache() {
     std::ifstream f(path);
     if (!f) return;
     std::string line;
-    // one entry per line: "key" : [waves_per_block, chunk]
+    // one entry per line: "key" : [waves_per_block, chunk, fewer_blocks]
     while (std::getline(f, line)) {
         size_t a = line.find('"');
         if (a == std::string::npos) continue;
@@ -506,9 +507,9 @@ void load_tune_cache() {
         size_t l = line.find('[', b);
         if (l == std::string::npos || line.find(']', l) == std::string::npos) continue;
         TuneChoice c;
-        if (sscanf(line.c_str() + l + 1, "%d , %d", &c.waves_per_block, &c.chunk) == 2 &&
+        if (sscanf(line.c_str() + l + 1, "%d , %d , %d", &c.waves_per_block, &c.chunk, &c.fewer_blocks) == 3 &&
             (c.waves_per_block == 1 || c.waves_per_block == 2 || c.waves_per_block == 4) && c.chunk >= 1 &&
-            c.chunk <= 64)
+            c.chunk <= 64 && c.fewer_blocks >= 0 && c.fewer_blocks < 8)
             g_tuned[line.substr(a + 1, b - a - 1)] = c;
     }
 }
@@ -521,7 +522,8 @@ void save_tune_cache() {
     f << "{\n";
     size_t i = 0;
     for (auto &kv : g_tuned) {
-        f << "  \"" << kv.first << "\" : [" << kv.second.waves_per_block << ", " << kv.second.chunk << "]"
+        f << "  \"" << kv.first << "\" : [" << kv.second.waves_per_block << ", " << kv.second.chunk << ", "
+          << kv.second.fewer_blocks << "]"
           << (++i < g_tuned.size() ? "," : "") << "\n";
     }
     f << "}\n";
@@ -534,13 +536,11 @@ int grid_for(const BatchState &b, const TuneChoice &c, int *grid) {
     const int e = b.state_fp32 ? persistent_blocks_per_cu(b.ws, c.waves_per_block, &blocks)
                                : mixed_blocks_per_cu(b.ws, c.waves_per_block, &blocks);
     if (e != 0 || blocks <= 0) return fail(LJSDE_EHIP, "occupancy query failed (%d)", e);
-    *grid = ncu * blocks;
+    // a grid below full occupancy can finish a batch in whole rounds
+    *grid = ncu * std::max(1, blocks - c.fewer_blocks);
     return LJSDE_OK;
 }
 
-// Work list of the FP64-state path: per job and class, the windows of that
-// class in row-major order, cut into groups of at most nw (the waves of one
-// workgroup share the class's spectra in LDS).
 // Work list of the persistent FP32 launch: groups of up to nw windows of one
 // class (they share the class tables staged in LDS). Windows are grouped
 // inside spatial tiles of the block grid, at least twice the class period on
@@ -866,7 +866,7 @@ int ljsde_autotune(const ljsde_job *jobs, int n_jobs, void *stream) {
     if (b->state_fp32)
         cands = {{1, 1}, {1, 2}, {1, 4}, {1, 8}, {2, 2}, {2, 4}, {4, 2}, {4, 4}};
     else
-        cands = {{1, 1}, {2, 1}, {4, 1}};
+        cands = {{1, 1, 0}, {2, 1, 0}, {4, 1, 0}, {2, 1, 1}, {4, 1, 1}};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
