@@ -91,7 +91,8 @@ typedef double v4f64 __attribute__((ext_vector_type(4)));
 template <typename XT>
 __device__ __forceinline__ void dft16_mfma(const XT *X, const signed char *Cd, const double *dft,
                                            double Pre[4][4], double Pim[4][4]) {
-    const int lane = threadIdx.x & 63;
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));  // per call: lane-derived addresses are not hoisted into registers
     const int r16 = lane & 15, q = lane >> 4;
     double x[4], gr[4], gi[4];
     int cd[4];
@@ -144,7 +145,8 @@ typedef float v4f32 __attribute__((ext_vector_type(4)));
 template <typename XT>
 __device__ __forceinline__ void dft16_splitbf16(const XT *X, const signed char *Cd, const double *dft,
                                                 float *lds, double Pre[4][4], double Pim[4][4]) {
-    const int lane = threadIdx.x & 63;
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));  // per call: lane-derived addresses are not hoisted into registers
     const int r16 = lane & 15, q = lane >> 4;
     const bool low = q >= 2;           // this lane feeds the second 16 of K
     const int k0 = 8 * (q & 1);        // first row/column (mod 16) of its 8 elements

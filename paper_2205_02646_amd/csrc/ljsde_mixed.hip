@@ -373,10 +373,10 @@ __device__ __forceinline__ void stage_tables(const KParams &p, const KJob &j, in
     if (with_tab) {
         float *twl = (float *)(glds + LL::offTw);
         double *tab = (double *)(glds + LL::offTab);
-        for (int e = threadIdx.x; e < 2 * WS; e += blockDim.x) tab[e] = p.c.dft[e];
-        for (int e = threadIdx.x; e < 4 * WS; e += blockDim.x) tab[2 * WS + e] = p.c.ew[e];
+        for (int e = tid; e < 2 * WS; e += blockDim.x) tab[e] = p.c.dft[e];
+        for (int e = tid; e < 4 * WS; e += blockDim.x) tab[2 * WS + e] = p.c.ew[e];
         // e^{-i theta k} and e^{-i theta (k + l)} per lane position
-        for (int e = threadIdx.x; e < QPL * 64; e += blockDim.x) {
+        for (int e = tid; e < QPL * 64; e += blockDim.x) {
             const int ln = e & 63, t = e >> 6;
             const int kap = (ln / WS) + (64 / WS) * t, lam = ln % WS;
             twl[e * 4 + 0] = (float)p.c.ew[2 * kap];
