@@ -21,6 +21,15 @@ blocking, fusion or reordering beyond what the equations state:
 * ``reconstruct`` -- the sliding-window driver (Sec. III): one model window of
   W x W high-resolution pixels per target block of B x B, step B.
 
+Pixel shapes (Sec. I, Sec. II eq. (1)): a sensor pixel integrates some
+quadrants of its 2x2 footprint. ``shape`` is a 4-bit mask of quadrant offsets
+d; the pixel with code o integrates the quadrants o XOR d for the bits d of
+the mask. Three-quarter sampling, the paper's layout, is ``THREE_QUARTER =
+0b1110`` (all quadrants but o, so the code names the opaque quadrant); quarter
+sampling (Sec. I: one transparent quadrant per pixel) is ``QUARTER = 0b0001``
+(the code names the transparent quadrant). RL-JSDE applies to any such
+periodically repeating layout (Sec. I).
+
 Readings where the paper is silent or garbled (each is listed with its reason
 in the design notes of the repository):
 
@@ -62,6 +71,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = [
+    "THREE_QUARTER",
+    "QUARTER",
     "central_offset",
     "window_sensor_origin",
     "local_window",
@@ -78,6 +89,15 @@ __all__ = [
     "measure_dense",
     "WindowTrace",
 ]
+
+
+THREE_QUARTER = 0b1110
+QUARTER = 0b0001
+
+
+def _integrates(code: int, a: int, b: int, shape: int) -> bool:
+    """Whether a pixel of this code integrates quadrant (row a, column b)."""
+    return bool((shape >> ((2 * a + b) ^ code)) & 1)
 
 
 # ----------------------------------------------------------------------------
@@ -133,10 +153,12 @@ def local_window(y: np.ndarray, tile: np.ndarray, bi: int, bj: int, W: int, B: i
 # Operators of Sec. II-IV
 # ----------------------------------------------------------------------------
 
-def local_measurement_operator(codes: np.ndarray, valid: np.ndarray, W: int) -> np.ndarray:
+def local_measurement_operator(codes: np.ndarray, valid: np.ndarray, W: int,
+                               shape: int = THREE_QUARTER) -> np.ndarray:
     """A^local[m, eta, gamma] of eq. (4): sensor pixel m = (W/2) i' + j' sums
-    the three transparent quadrants of its footprint (rows 2i', 2i'+1, columns
-    2j', 2j'+1 of the window); absent pixels have an all-zero row."""
+    the quadrants of its footprint (rows 2i', 2i'+1, columns 2j', 2j'+1 of the
+    window) that its pixel shape integrates (the three transparent ones for
+    three-quarter sampling); absent pixels have an all-zero row."""
     Ws = W // 2
     A = np.zeros((Ws * Ws, W, W), dtype=np.float64)
     for ip in range(Ws):
@@ -144,11 +166,10 @@ def local_measurement_operator(codes: np.ndarray, valid: np.ndarray, W: int) -> 
             if not valid[ip, jp]:
                 continue
             o = int(codes[ip, jp])
-            ao, bo = o >> 1, o & 1
             m = ip * Ws + jp
             for a in (0, 1):
                 for b in (0, 1):
-                    if (a, b) != (ao, bo):
+                    if _integrates(o, a, b, shape):
                         A[m, 2 * ip + a, 2 * jp + b] = 1.0
     return A
 
@@ -304,8 +325,9 @@ def synthesize_block(coeffs, W: int, B: int) -> np.ndarray:
 # ----------------------------------------------------------------------------
 
 class _Cache:
-    def __init__(self, W, rho, form):
+    def __init__(self, W, rho, form, shape=THREE_QUARTER):
         self.W = W
+        self.shape = shape
         self.Phi = fourier_basis(W)
         self.w_full = spatial_weights(W, rho)
         self.form = form
@@ -315,7 +337,7 @@ class _Cache:
         key = (codes.tobytes(), valid.tobytes())
         hit = self.store.get(key)
         if hit is None:
-            A = local_measurement_operator(codes, valid, self.W)
+            A = local_measurement_operator(codes, valid, self.W, self.shape)
             a = basis_responses(A, self.Phi)
             w = self.w_full * valid.reshape(-1)
             if self.form == "RL":
@@ -327,11 +349,11 @@ class _Cache:
 
 
 def reconstruct(y, tile, W=32, B=4, iters=100, rho=0.7, gamma=0.5, form="L",
-                q_mode="fsr", blocks=None, traces=False):
+                q_mode="fsr", blocks=None, traces=False, shape=THREE_QUARTER):
     """Reconstruct the 2x-resolution image from sensor read-out ``y``.
 
-    ``tile`` is the opaque-quadrant pattern tile (sensor pixel (i, j) uses
-    ``tile[i % pr, j % pc]``). ``form`` is ``"L"`` (L-JSDE) or ``"RL"``
+    ``tile`` is the pattern tile of quadrant codes (sensor pixel (i, j) uses
+    ``tile[i % pr, j % pc]``); ``shape`` the pixel shape (module docstring). ``form`` is ``"L"`` (L-JSDE) or ``"RL"``
     (RL-JSDE, per-class B, C, D cached by the content of the local measurement
     matrix). ``blocks`` restricts the work to a list of (bi, bj) target
     blocks; other output pixels are NaN. Returns the image, and with
@@ -344,7 +366,7 @@ def reconstruct(y, tile, W=32, B=4, iters=100, rho=0.7, gamma=0.5, form="L",
     if M % B or N % B:
         raise ValueError("image sides must be multiples of the block size")
     q = frequency_weights(W, q_mode)
-    cache = _Cache(W, rho, form)
+    cache = _Cache(W, rho, form, shape)
     if blocks is None:
         blocks = [(bi, bj) for bi in range(M // B) for bj in range(N // B)]
     out = np.full((M, N), np.nan)
@@ -365,7 +387,7 @@ def reconstruct(y, tile, W=32, B=4, iters=100, rho=0.7, gamma=0.5, form="L",
     return (out, all_traces) if traces else out
 
 
-def measure_dense(f: np.ndarray, tile: np.ndarray) -> np.ndarray:
+def measure_dense(f: np.ndarray, tile: np.ndarray, shape: int = THREE_QUARTER) -> np.ndarray:
     """eq. (1) with an explicitly built global measurement matrix A[i, alpha, beta]
     (for tiny images only): y_i = sum A_i f."""
     M, N = f.shape
@@ -377,6 +399,6 @@ def measure_dense(f: np.ndarray, tile: np.ndarray) -> np.ndarray:
             o = int(tile[i % pr, j % pc])
             for a in (0, 1):
                 for b in (0, 1):
-                    if (a, b) != (o >> 1, o & 1):
+                    if _integrates(o, a, b, shape):
                         A[i * Ns + j, 2 * i + a, 2 * j + b] = 1.0
     return np.tensordot(A, f, axes=([1, 2], [0, 1])).reshape(Ms, Ns)

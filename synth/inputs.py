@@ -10,9 +10,14 @@ Conventions
 -----------
 * Images are indexed ``[row, col]`` with the origin in the upper-left corner.
   Sizes quoted as ``WxH`` are width x height, i.e. ``H`` rows.
-* A pattern is a ``uint8`` tile of opaque-quadrant codes ``o = 2*a + b``
-  (``a`` = row offset, ``b`` = column offset of the opaque quadrant inside the
-  2x2 footprint). Sensor pixel ``(i, j)`` uses ``tile[i % pr, j % pc]``.
+* A pattern is a ``uint8`` tile of quadrant codes ``o = 2*a + b``
+  (``a`` = row offset, ``b`` = column offset inside the 2x2 footprint). Sensor
+  pixel ``(i, j)`` uses ``tile[i % pr, j % pc]``.
+* A pixel shape is a 4-bit mask of quadrant offsets ``d``: the pixel of code
+  ``o`` collects light on the quadrants ``o ^ d`` for the bits ``d`` of the
+  mask. ``THREE_QUARTER = 0b1110`` (all quadrants but ``o``: the code names
+  the opaque quadrant) is the default; ``QUARTER = 0b0001`` (only ``o``: the
+  code names the transparent quadrant).
 * Grey range is 0..255.
 
 Workload recipe (stand-in for the paper's natural-image test set, which is not
@@ -33,7 +38,12 @@ __all__ = [
     "make_case",
     "CONFIGS",
     "batch_cases",
+    "THREE_QUARTER",
+    "QUARTER",
 ]
+
+THREE_QUARTER = 0b1110
+QUARTER = 0b0001
 
 
 def _streams(seed: int):
@@ -117,13 +127,14 @@ def random_pattern(pat_rows: int, pat_cols: int, seed: int = 0) -> np.ndarray:
     return g_pat.integers(0, 4, size=(pat_rows, pat_cols)).astype(np.uint8)
 
 
-def sense(image: np.ndarray, tile: np.ndarray) -> np.ndarray:
-    """Three-quarter-sampling sensor read-out of a high-resolution image.
+def sense(image: np.ndarray, tile: np.ndarray, shape: int = THREE_QUARTER) -> np.ndarray:
+    """Sensor read-out of a high-resolution image.
 
-    Each sensor pixel ``(i, j)`` returns the sum of the three transparent
-    quadrants of ``image[2i:2i+2, 2j:2j+2]``: the whole 2x2 sum minus the
-    opaque quadrant selected by the tile code. Works for float and complex
-    images; the result has shape ``(rows/2, cols/2)``.
+    Each sensor pixel ``(i, j)`` returns the sum of the quadrants of
+    ``image[2i:2i+2, 2j:2j+2]`` that its shape collects: for three-quarter
+    sampling the whole 2x2 sum minus the opaque quadrant selected by the tile
+    code. Works for float and complex images; the result has shape
+    ``(rows/2, cols/2)``.
     """
     rows, cols = image.shape
     if rows % 2 or cols % 2:
@@ -132,12 +143,13 @@ def sense(image: np.ndarray, tile: np.ndarray) -> np.ndarray:
     quads = image.reshape(sr, 2, sc, 2).transpose(0, 2, 1, 3)  # [i, j, a, b]
     pr, pc = tile.shape
     codes = tile[np.arange(sr)[:, None] % pr, np.arange(sc)[None, :] % pc]
-    total = quads.sum(axis=(2, 3))
-    a = (codes >> 1).astype(np.intp)
-    b = (codes & 1).astype(np.intp)
     ii, jj = np.meshgrid(np.arange(sr), np.arange(sc), indexing="ij")
-    opaque = quads[ii, jj, a, b]
-    return total - opaque
+    out = np.zeros((sr, sc), dtype=np.result_type(image.dtype, np.float64))
+    for d in range(4):
+        if (shape >> d) & 1:
+            q = codes.astype(np.intp) ^ d
+            out = out + quads[ii, jj, q >> 1, q & 1]
+    return out
 
 
 # Workloads. ``pattern`` is the tile size in sensor pixels; None means the
@@ -157,12 +169,13 @@ RHO = 0.7
 GAMMA = 0.5
 
 
-def make_case(rows: int, cols: int, pattern, seed: int = 0, noise: float = 0.0):
+def make_case(rows: int, cols: int, pattern, seed: int = 0, noise: float = 0.0,
+              shape: int = THREE_QUARTER):
     """Build one reconstruction case.
 
     Returns a dict with ``clean`` (float64 reference image), ``tile`` (uint8
-    opaque-quadrant tile) and ``y`` (float64 sensor read-out of the observed,
-    possibly noisy, image).
+    quadrant-code tile) and ``y`` (float64 sensor read-out, with pixel shape
+    ``shape``, of the observed, possibly noisy, image).
     """
     clean, observed = synthetic_image(rows, cols, seed=seed, noise_sigma=noise)
     if pattern is None:
@@ -170,7 +183,7 @@ def make_case(rows: int, cols: int, pattern, seed: int = 0, noise: float = 0.0):
     else:
         pr, pc = (pattern, pattern) if np.isscalar(pattern) else pattern
         tile = random_pattern(pr, pc, seed=seed)
-    y = sense(observed, tile)
+    y = sense(observed, tile, shape)
     return dict(clean=clean, tile=tile, y=y)
 
 
