@@ -12,7 +12,8 @@ Other workloads (``--workload``): frame2048 (2048x2048 + N(0, 2^2) noise,
 8x8-sensor tile, 250 iterations), frame8192 (8192x8192, 16x16-sensor tile,
 250 iterations), paper1200 (1200x1200, 16x16-sensor tile, 100 iterations),
 batch64 (64 images of uneven size, each with its own pattern of period 2, 4
-or 8, 100 iterations, one batched launch).
+or 8, 100 iterations, one batched launch), quarter512 (the 512x512 frame
+under quarter sampling: one transparent quadrant per pixel).
 
 Prints one JSON line.
 """
@@ -49,6 +50,9 @@ WORKLOADS = {
                       desc="1200x1200 frame, recurrent 16x16-sensor pattern (period 32 px)"),
     "batch64": dict(kind="batch", n=64, iters=100,
                     desc="64 images of uneven size, own patterns of period 2/4/8"),
+    "quarter512": dict(kind="frame", rows=512, cols=512, period=4, iters=100, noise=0.0, shape=0x1,
+                       desc="512x512 frame, quarter sampling (one transparent quadrant per pixel), "
+                            "recurrent 4x4-sensor pattern"),
 }
 
 
@@ -74,18 +78,19 @@ def load_traffic(workload: str):
 
 
 def _oracle_worker(args):
-    y, tile, blocks, iters = args
+    y, tile, blocks, iters, shape = args
     from oracle import ljsde_oracle as O
     try:
         from threadpoolctl import threadpool_limits
         threadpool_limits(1)
     except Exception:  # pragma: no cover
         pass
-    out = O.reconstruct(y, tile, W=W, B=B, iters=iters, rho=RHO, gamma=GAMMA, form="RL", blocks=blocks)
+    out = O.reconstruct(y, tile, W=W, B=B, iters=iters, rho=RHO, gamma=GAMMA, form="RL", blocks=blocks,
+                        shape=shape)
     return [(bi, bj, out[B * bi:B * bi + B, B * bj:B * bj + B]) for bi, bj in blocks]
 
 
-def cpu_baseline(y, tile, iters: int, n_windows: int, seed: int = 1, label: str = ""):
+def cpu_baseline(y, tile, iters: int, n_windows: int, seed: int = 1, label: str = "", shape: int = 0xE):
     """Time the FP64 oracle (RL-JSDE form) on a random sample of windows over
     the host cores; returns (record, {block: output})."""
     import multiprocessing as mp
@@ -98,7 +103,7 @@ def cpu_baseline(y, tile, iters: int, n_windows: int, seed: int = 1, label: str 
     chunks = [blocks[k::cores] for k in range(cores)]
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores) as pool:
-        parts = pool.map(_oracle_worker, [(y, tile, c, iters) for c in chunks if c])
+        parts = pool.map(_oracle_worker, [(y, tile, c, iters, shape) for c in chunks if c])
     dt = time.perf_counter() - t0
     res = {(bi, bj): blk for part in parts for bi, bj, blk in part}
     rec = {"value": n_windows * B * B / dt / 1e6, "unit": "MP/s", "cores": cores, "kind": "oracle",
@@ -110,7 +115,8 @@ def cpu_baseline(y, tile, iters: int, n_windows: int, seed: int = 1, label: str 
 
 def build_inputs(wl: dict):
     if wl["kind"] == "frame":
-        return [make_case(wl["rows"], wl["cols"], wl["period"], seed=0, noise=wl["noise"])]
+        return [make_case(wl["rows"], wl["cols"], wl["period"], seed=0, noise=wl["noise"],
+                          shape=wl.get("shape", 0xE))]
     return batch_cases(wl["n"], seed=0)
 
 
@@ -133,6 +139,7 @@ def main():
 
     wl = WORKLOADS[args.workload]
     iters = wl["iters"]
+    shape = wl.get("shape", 0xE)
     cases = build_inputs(wl)
     y32h = [c["y"].astype(np.float32) for c in cases]
 
@@ -141,8 +148,8 @@ def main():
     if not args.no_oracle:
         label = wl["desc"].split(",")[0] if wl["kind"] == "frame" else "first image of the batch"
         oracle_rec, oracle_blocks = cpu_baseline(y32h[0].astype(np.float64), cases[0]["tile"], iters,
-                                                 args.oracle_windows, label=label)
-        _, oracle64_blocks = cpu_baseline(cases[0]["y"], cases[0]["tile"], iters, 128, seed=2)
+                                                 args.oracle_windows, label=label, shape=shape)
+        _, oracle64_blocks = cpu_baseline(cases[0]["y"], cases[0]["tile"], iters, 128, seed=2, shape=shape)
 
     # the autotuner's choice is read back from its cache file for the report
     import tempfile
@@ -157,11 +164,12 @@ def main():
     jobs, runs64 = [], []
     for c, y in zip(cases, y32h):
         rows, cols = 2 * y.shape[0], 2 * y.shape[1]
-        p32 = ljsde.plan(c["tile"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA)
+        p32 = ljsde.plan(c["tile"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA, shape=shape)
         jobs.append((torch.from_numpy(y).to(dev), p32,
                      torch.empty((rows, cols), dtype=torch.float32, device=dev)))
         if not args.no_fp64:
-            p64 = ljsde.plan(c["tile"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA, fp64=True)
+            p64 = ljsde.plan(c["tile"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA, fp64=True,
+                             shape=shape)
             runs64.append((torch.from_numpy(c["y"]).to(dev), p64,
                            torch.empty((rows, cols), dtype=torch.float64, device=dev)))
 

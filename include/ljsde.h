@@ -64,10 +64,27 @@ enum {
 };
 
 /*
+ * Pixel shape (Sec. I; Sec. II eq. (1): any such layout is a measurement
+ * matrix). Flag bits 8..11 hold a mask of quadrant offsets d: the sensor
+ * pixel of code o collects light on the quadrants o XOR d (quadrant index
+ * 2 * row + column inside its 2x2 footprint) for the bits d that are set.
+ * 0 means three-quarter sampling. Kernels exist for three-quarter sampling
+ * (L-shaped pixels, the code names the opaque quadrant) and quarter sampling
+ * (the code names the one transparent quadrant); other masks are
+ * LJSDE_EUNSUPPORTED, and so are LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32
+ * with quarter sampling.
+ */
+#define LJSDE_SHAPE(mask) ((((unsigned)(mask)) & 15u) << 8)
+enum {
+    LJSDE_SHAPE_THREE_QUARTER = 0xE00,
+    LJSDE_SHAPE_QUARTER = 0x100
+};
+
+/*
  * ljsde_plan -- validate and register a reconstruction plan.
  *
- * Defines the local measurement matrices of a recurrent three-quarter
- * sampling sensor (Sec. II, Sec. IV: all windows with the same local
+ * Defines the local measurement matrices of a recurrent three-quarter (or
+ * quarter) sampling sensor (Sec. II, Sec. IV: all windows with the same local
  * measurement matrix share their precomputed tables).
  *  pattern   host, pat_rows x pat_cols uint8 codes (copied; the caller keeps
  *            ownership). A non-recurrent sensor passes the whole sensor.
@@ -79,7 +96,8 @@ enum {
  *  rho       spatial weight base of w_m = rho^d (eq. (8)), 0 < rho <= 1.
  *  gamma     orthogonality deficiency compensation gamma_odc of eq. (15),
  *            0 < gamma < 2.
- *  flags     exactly one of LJSDE_FP64 / LJSDE_FP32, plus options.
+ *  flags     exactly one of LJSDE_FP64 / LJSDE_FP32, plus options and an
+ *            optional pixel shape (LJSDE_SHAPE_*).
  * Returns a pattern id >= 0, or a negative status. Needs no GPU: tables for
  * an image size are built and uploaded on its first reconstruction.
  */

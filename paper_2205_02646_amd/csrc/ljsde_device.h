@@ -36,6 +36,36 @@ constexpr int DPP_QUAD_XOR2 = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int DPP_ROW_HALF_MIRROR = 0x141;
 constexpr int DPP_ROW_MIRROR = 0x140;
 
+// Pixel shapes (Sec. I; Sec. II eq. (1)): a pixel of code o collects light on
+// the quadrants o ^ d for the bits d of a 4-bit mask. Three-quarter sampling
+// (every quadrant but the opaque one, o) is 0xE; quarter sampling (only the
+// transparent quadrant, o) is 0x1.
+constexpr int SHAPE_THREE_QUARTER = 0xE;
+constexpr int SHAPE_QUARTER = 0x1;
+
+// Per-quadrant sums of the projection. With H_o = sum_{d in mask} e_{o ^ d}
+// (e_q the response of quadrant q), sum_o conj(H_o) P_o = sum_q conj(e_q) Q_q
+// where Q_q = sum_{d in mask} P_{q ^ d}.
+template <int MASK, typename T>
+__device__ __forceinline__ void shape_sums(const C2<T> P[4], C2<T> Q[4]) {
+    if constexpr (MASK == SHAPE_THREE_QUARTER) {
+        const C2<T> sp = {P[0].re + P[1].re + P[2].re + P[3].re, P[0].im + P[1].im + P[2].im + P[3].im};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Q[q] = {sp.re - P[q].re, sp.im - P[q].im};
+    } else if constexpr (MASK == SHAPE_QUARTER) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Q[q] = P[q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            Q[q] = {T(0), T(0)};
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                if ((MASK >> d) & 1) Q[q] = {Q[q].re + P[q ^ d].re, Q[q].im + P[q ^ d].im};
+        }
+    }
+}
+
 // Maximum of unsigned keys over the wavefront (a wave-uniform value): a
 // max-butterfly inside each row of 16 lanes, then the four row maxima.
 __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {

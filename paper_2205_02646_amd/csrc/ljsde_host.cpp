@@ -95,6 +95,7 @@ struct Plan {
     int pr = 0, pc = 0, W = 0, B = 0, Ws = 0, iters = 0;
     double rho = 0, gamma = 0, tau = 0;
     unsigned flags = 0;
+    int shape = 0xE;                    // pixel-shape mask of quadrant offsets
     ClassLayout lay{};
     std::vector<double> w, ew, dft, q, H;  // class-independent FP64 tables
     int device = -1;
@@ -148,23 +149,24 @@ void build_constants(Plan &p) {
         p.dft[2 * k] = std::cos(a);
         p.dft[2 * k + 1] = std::sin(a);
     }
-    // H_o(sigma, rho) = sum over the three transparent quadrants (a, b) of
-    // e^{i theta (a sigma + b rho)} = box response - opaque quadrant's term
+    // H_o(sigma, rho) = sum over the quadrants (a, b) that the pixel of code o
+    // collects (q = 2a + b with bit q ^ o of the shape mask set) of
+    // e^{i theta (a sigma + b rho)}; for three-quarter sampling, the box
+    // response minus the opaque quadrant's term
     p.H.resize((size_t)W * W * 8);
     for (int sg = 0; sg < W; ++sg)
-        for (int rh = 0; rh < W; ++rh) {
-            const double eur = p.ew[2 * sg], eui = p.ew[2 * sg + 1];
-            const double evr = p.ew[2 * rh], evi = p.ew[2 * rh + 1];
-            const int uv = (sg + rh) % W;
-            const double hbr = (1 + eur) * (1 + evr) - eui * evi;
-            const double hbi = (1 + eur) * evi + eui * (1 + evr);
-            const double Hr[4] = {hbr - 1.0, hbr - evr, hbr - eur, hbr - p.ew[2 * uv]};
-            const double Hi[4] = {hbi, hbi - evi, hbi - eui, hbi - p.ew[2 * uv + 1]};
+        for (int rh = 0; rh < W; ++rh)
             for (int o = 0; o < 4; ++o) {
-                p.H[((size_t)(sg * W + rh) * 4 + o) * 2] = Hr[o];
-                p.H[((size_t)(sg * W + rh) * 4 + o) * 2 + 1] = Hi[o];
+                double hr = 0.0, hi = 0.0;
+                for (int q = 0; q < 4; ++q) {
+                    if (!((p.shape >> (q ^ o)) & 1)) continue;
+                    const int ph = ((q >> 1) * sg + (q & 1) * rh) % W;
+                    hr += p.ew[2 * ph];
+                    hi += p.ew[2 * ph + 1];
+                }
+                p.H[((size_t)(sg * W + rh) * 4 + o) * 2] = hr;
+                p.H[((size_t)(sg * W + rh) * 4 + o) * 2 + 1] = hi;
             }
-        }
     p.q.resize(W * W);
     const double qmax = std::sqrt(2.0) * W / 2.0;
     for (int s = 0; s < W; ++s)
@@ -403,6 +405,7 @@ KParams make_params(const Plan &p) {
     k.ecoef = 2 * p.gamma - p.gamma * p.gamma;
     k.tau = p.tau;
     k.dft_bf16 = (p.flags & LJSDE_DFT_SPLITBF16) != 0 ? 1 : 0;
+    k.shape = p.shape;
     k.c.w = p.d_consts;
     k.c.ew = p.d_consts + p.w.size();
     k.c.dft = p.d_consts + p.w.size() + p.ew.size();
@@ -485,7 +488,7 @@ std::string tune_key(const Plan &p, bool state_fp32, long long total_windows, in
     while ((1LL << wb) < total_windows) ++wb;
     std::ostringstream os;
     os << prop.gcnArchName << "/W" << p.W << "/B" << p.B << "/it" << p.iters
-       << (state_fp32 ? "/fp32" : "/fp32s64") << "/c" << bucket << "/n" << wb;
+       << (state_fp32 ? "/fp32" : "/fp32s64") << "/s" << p.shape << "/c" << bucket << "/n" << wb;
     return os.str();
 }
 
@@ -772,7 +775,8 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, i
     if (iters < 1) return fail(LJSDE_EINVAL, "iters %d must be >= 1", iters);
     if (!(rho > 0.0 && rho <= 1.0)) return fail(LJSDE_EINVAL, "rho %g must be in (0, 1]", rho);
     if (!(gamma > 0.0 && gamma < 2.0)) return fail(LJSDE_EINVAL, "gamma %g must be in (0, 2)", gamma);
-    const unsigned known = LJSDE_FP64 | LJSDE_FP32 | LJSDE_DFT_SPLITBF16 | LJSDE_Q_ONES | LJSDE_STATE_FP32;
+    const unsigned known = LJSDE_FP64 | LJSDE_FP32 | LJSDE_DFT_SPLITBF16 | LJSDE_Q_ONES | LJSDE_STATE_FP32 |
+                           LJSDE_SHAPE(15);
     if (flags & ~known) return fail(LJSDE_EINVAL, "unknown flags 0x%x", flags & ~known);
     if (((flags & LJSDE_FP64) != 0) == ((flags & LJSDE_FP32) != 0))
         return fail(LJSDE_EINVAL, "exactly one of LJSDE_FP64 / LJSDE_FP32 is required");
@@ -785,6 +789,13 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, i
     if (!(block == 4 || block == 8))
         return fail(LJSDE_EUNSUPPORTED, "no kernel for block %d (have 4, 8)", block);
     if (iters > 32767) return fail(LJSDE_EUNSUPPORTED, "iters %d above 32767", iters);
+    int shape = (int)((flags >> 8) & 15u);
+    if (shape == 0) shape = 0xE;
+    if (shape != 0xE && shape != 0x1)
+        return fail(LJSDE_EUNSUPPORTED,
+                    "pixel shape mask 0x%x: kernels exist for three-quarter (0xE) and quarter (0x1) sampling", shape);
+    if (shape == 0x1 && (flags & (LJSDE_DFT_SPLITBF16 | LJSDE_STATE_FP32)))
+        return fail(LJSDE_EUNSUPPORTED, "LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32 exist for three-quarter sampling only");
     auto p = std::make_unique<Plan>();
     p->pattern.assign(pattern, pattern + (size_t)pat_rows * pat_cols);
     p->pr = pat_rows;
@@ -796,6 +807,7 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, i
     p->rho = rho;
     p->gamma = gamma;
     p->flags = flags;
+    p->shape = shape;
     p->lay = make_layout(p->W, p->Ws);
     build_constants(*p);
     std::lock_guard<std::mutex> lk(g_mu);

@@ -11,8 +11,8 @@ struct DevConsts {
     const double *w;    // [Ws*Ws] spatial weights w_m = rho^d_m (eq. (8))
     const double *ew;   // [W][2]  exp(+i 2 pi k / W), k < W
     const double *dft;  // [Ws][2] exp(-i 2 pi k / Ws), k < Ws
-    const double *H;    // [W*W][4][2] H_o(sigma, rho): response of the L-shaped pixel of
-                        // orientation o to the basis function (sigma, rho)
+    const double *H;    // [W*W][4][2] H_o(sigma, rho): response of the pixel of code o
+                        // (its shape's quadrants) to the basis function (sigma, rho)
 };
 
 // Byte offsets inside one class block of the device table.
@@ -34,6 +34,8 @@ struct KParams {
     double ecoef;  // 2 gamma - gamma^2
     double tau;    // energy floor (0 = off)
     int dft_bf16;  // window DFT with split-BF16 MFMA products (FP32 plans)
+    int shape;     // pixel-shape mask (0xE three-quarter, 0x1 quarter): picks
+                   // the kernel instantiation on the host
     DevConsts c;
     ClassLayout lay;
 };

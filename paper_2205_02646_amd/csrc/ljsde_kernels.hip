@@ -8,8 +8,10 @@
 // from which the projected residual of eq. (12) follows for every frequency
 // (sigma, rho) = (k + Ws a, l + Ws b) as
 //     R(sigma, rho) = sum_o conj(H_o(sigma, rho)) P_o(k, l),
-// with H_o the response of the L-shaped pixel of orientation o to the basis
-// function (the box response of the 2x2 footprint minus the opaque quadrant).
+// with H_o the response of the pixel of code o to the basis function: for the
+// L-shaped pixels of three-quarter sampling the box response of the 2x2
+// footprint minus the opaque quadrant, for quarter sampling the response of
+// the one transparent quadrant.
 // Selecting (u, v) by eq. (11) and taking the step of eqs. (15)-(16) changes
 // every P_o by the orientation's weighted-mask spectrum S_o shifted by (u, v)
 // (eq. (17) in factorised form):
@@ -45,7 +47,7 @@ struct WinLds {
     static constexpr size_t bytes = (size_t)NPOS * 8 * sizeof(T) + NPOS * sizeof(T) + NPOS;
 };
 
-template <typename T, int WS>
+template <typename T, int WS, int SHAPE>
 __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, int bi, int bj,
                                                long long win_local, char *lds) {
     constexpr int W = 2 * WS;
@@ -206,13 +208,11 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
                     P[t][o].im -= g4[o].re * si + g4[o].im * sr;
                 }
             }
-            // project: R(a, b) = sum_q (-1)^(qa a + qb b) e^{-i theta (qa k + qb l)} (sum P - P_q)
-            const C2<T> sp = {P[t][0].re + P[t][1].re + P[t][2].re + P[t][3].re,
-                              P[t][0].im + P[t][1].im + P[t][2].im + P[t][3].im};
-            const C2<T> q0 = {sp.re - P[t][0].re, sp.im - P[t][0].im};
-            const C2<T> q1 = {sp.re - P[t][1].re, sp.im - P[t][1].im};
-            const C2<T> q2 = {sp.re - P[t][2].re, sp.im - P[t][2].im};
-            const C2<T> q3 = {sp.re - P[t][3].re, sp.im - P[t][3].im};
+            // project: R(a, b) = sum_q (-1)^(qa a + qb b) e^{-i theta (qa k + qb l)} Q_q with the
+            // per-quadrant sums of the pixel shape (sum P - P_q for three-quarter sampling)
+            C2<T> Q[4];
+            shape_sums<SHAPE, T>(P[t], Q);
+            const C2<T> q0 = Q[0], q1 = Q[1], q2 = Q[2], q3 = Q[3];
             const C2<T> u1 = {tl.re * q1.re - tl.im * q1.im, tl.re * q1.im + tl.im * q1.re};
             const C2<T> u2 = {tk[t].re * q2.re - tk[t].im * q2.im, tk[t].re * q2.im + tk[t].im * q2.re};
             const C2<T> u3 = {tkl[t].re * q3.re - tkl[t].im * q3.im,
@@ -312,14 +312,14 @@ struct Occ {
     static constexpr int waves = sizeof(T) == 8 ? 2 : 3;
 };
 
-template <typename T, int WS>
+template <typename T, int WS, int SHAPE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Occ<T>::waves))) void plain_kernel(KParams p,
                                                                                                         KJob j) {
     extern __shared__ char lds[];
     const long long w = blockIdx.x;
     const long long nwin = (long long)j.nbi * j.nbj;
     if (w >= nwin) return;
-    process_window<T, WS>(p, j, (int)(w / j.nbj), (int)(w % j.nbj), w, lds);
+    process_window<T, WS, SHAPE>(p, j, (int)(w / j.nbj), (int)(w % j.nbj), w, lds);
 }
 
 __global__ void reset_counter_kernel(unsigned int *counters) {
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
             }
             const KJob j = jobs[lo];
             const long long lw = gw - j.win_begin;
-            process_window<T, WS>(p, j, (int)(lw / j.nbj), (int)(lw % j.nbj), lw, mylds);
+            process_window<T, WS, SHAPE_THREE_QUARTER>(p, j, (int)(lw / j.nbj), (int)(lw % j.nbj), lw, mylds);
         }
     }
 }
@@ -360,21 +360,27 @@ size_t lds_bytes_per_wave(int ws, bool fp64) {
     return fp64 ? WinLds<double, 8>::bytes : WinLds<float, 8>::bytes;
 }
 
-template <typename T, int WS>
+template <typename T, int WS, int SHAPE>
 static int launch_plain_t(const KParams &p, const KJob &job, void *stream) {
     const long long nwin = (long long)job.nbi * job.nbj;
     if (nwin <= 0) return 0;
     const size_t lds = WinLds<T, WS>::bytes;
-    plain_kernel<T, WS><<<dim3((unsigned)nwin), dim3(64), lds, (hipStream_t)stream>>>(p, job);
+    plain_kernel<T, WS, SHAPE><<<dim3((unsigned)nwin), dim3(64), lds, (hipStream_t)stream>>>(p, job);
     return (int)hipGetLastError();
 }
 
+// FP64 plans: three-quarter and quarter sampling
 int launch_plain_f64(const KParams &p, const KJob &job, int ws, void *stream) {
-    return ws == 16 ? launch_plain_t<double, 16>(p, job, stream) : launch_plain_t<double, 8>(p, job, stream);
+    constexpr int TQ = SHAPE_THREE_QUARTER, QS = SHAPE_QUARTER;
+    if (p.shape == QS)
+        return ws == 16 ? launch_plain_t<double, 16, QS>(p, job, stream) : launch_plain_t<double, 8, QS>(p, job, stream);
+    return ws == 16 ? launch_plain_t<double, 16, TQ>(p, job, stream) : launch_plain_t<double, 8, TQ>(p, job, stream);
 }
 
+// FP32-state plans (three-quarter sampling only)
 int launch_plain_f32(const KParams &p, const KJob &job, int ws, void *stream) {
-    return ws == 16 ? launch_plain_t<float, 16>(p, job, stream) : launch_plain_t<float, 8>(p, job, stream);
+    constexpr int TQ = SHAPE_THREE_QUARTER;
+    return ws == 16 ? launch_plain_t<float, 16, TQ>(p, job, stream) : launch_plain_t<float, 8, TQ>(p, job, stream);
 }
 
 int launch_reset_counter(unsigned int *counter, void *stream) {

@@ -49,14 +49,14 @@ struct MixedLds {
 };
 
 // R(a, b) for the four frequencies (k + Ws a, l + Ws b) of one position:
-// R = sum_q (-1)^(qa a + qb b) e^{-i theta (qa k + qb l)} (sum_o P_o - P_q).
-template <typename T>
+// R = sum_q (-1)^(qa a + qb b) e^{-i theta (qa k + qb l)} Q_q, with the
+// per-quadrant sums Q_q of the pixel shape (sum_o P_o - P_q for the L pixels
+// of three-quarter sampling).
+template <typename T, int SHAPE>
 __device__ __forceinline__ void project4(const C2<T> P[4], C2<T> tl, C2<T> tk, C2<T> tkl, C2<T> R[4]) {
-    const C2<T> sp = {P[0].re + P[1].re + P[2].re + P[3].re, P[0].im + P[1].im + P[2].im + P[3].im};
-    const C2<T> q0 = {sp.re - P[0].re, sp.im - P[0].im};
-    const C2<T> q1 = {sp.re - P[1].re, sp.im - P[1].im};
-    const C2<T> q2 = {sp.re - P[2].re, sp.im - P[2].im};
-    const C2<T> q3 = {sp.re - P[3].re, sp.im - P[3].im};
+    C2<T> Q[4];
+    shape_sums<SHAPE, T>(P, Q);
+    const C2<T> q0 = Q[0], q1 = Q[1], q2 = Q[2], q3 = Q[3];
     const C2<T> u1 = {tl.re * q1.re - tl.im * q1.im, tl.re * q1.im + tl.im * q1.re};
     const C2<T> u2 = {tk.re * q2.re - tk.im * q2.im, tk.re * q2.im + tk.im * q2.re};
     const C2<T> u3 = {tkl.re * q3.re - tkl.im * q3.im, tkl.re * q3.im + tkl.im * q3.re};
@@ -68,7 +68,7 @@ __device__ __forceinline__ void project4(const C2<T> P[4], C2<T> tl, C2<T> tk, C
     R[3] = {s1.re - s2.re, s1.im - s2.im};  // (1, 1)
 }
 
-template <int WS, bool BF16>
+template <int WS, bool BF16, int SHAPE>
 __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJob &j, int bi, int bj,
                                                      long long win_local, char *wlds, const char *glds) {
     using LL = MixedLds<WS>;
@@ -200,7 +200,7 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
             C2<float> Pf[4], R[4];
 #pragma unroll
             for (int o = 0; o < 4; ++o) Pf[o] = {(float)P[t][o].re, (float)P[t][o].im};
-            project4<float>(Pf, tl, C2<float>{t4.x, t4.y}, C2<float>{t4.z, t4.w}, R);
+            project4<float, SHAPE>(Pf, tl, C2<float>{t4.x, t4.y}, C2<float>{t4.z, t4.w}, R);
             const float qd[4] = {q4.x, q4.y, q4.z, q4.w};
             unsigned key[4];
 #pragma unroll
@@ -238,7 +238,7 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
                 const C2<double> dtkl = {ew[2 * (kap + lam)], -ew[2 * (kap + lam) + 1]};
                 const C2<double> dtl = {ew[2 * lam], -ew[2 * lam + 1]};
                 C2<double> R[4];
-                project4<double>(P[t], dtl, dtk, dtkl, R);
+                project4<double, SHAPE>(P[t], dtl, dtk, dtkl, R);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const int a = c >> 1, b = c & 1;
@@ -388,7 +388,7 @@ __device__ __forceinline__ void stage_tables(const KParams &p, const KJob &j, in
 }
 
 // One window per workgroup (used for selection diagnostics).
-template <int WS, bool BF16>
+template <int WS, bool BF16, int SHAPE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void mixed_window_kernel(KParams p, KJob j) {
     extern __shared__ __align__(16) char lds[];
     using L = MixedLds<WS>;
@@ -398,7 +398,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void mi
     const int bi = (int)(w / j.nbj), bj = (int)(w % j.nbj);
     stage_tables<WS>(p, j, j.rowcls[bi] * j.ncolk + j.colcls[bj], lds, true);
     __syncthreads();
-    process_window_mixed<WS, BF16>(p, j, bi, bj, w, lds + L::shared_bytes, lds);
+    process_window_mixed<WS, BF16, SHAPE>(p, j, bi, bj, w, lds + L::shared_bytes, lds);
 }
 
 // Persistent: workgroups pull groups of up to NW same-class windows. The
@@ -407,7 +407,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void mi
 // (workgroups are dealt to the XCDs round-robin) and then the others, so the
 // measurements and output lines of a tile stay in one XCD's L2. Every group
 // index is claimed exactly once whatever the actual placement.
-template <int WS, int NW, bool BF16>
+template <int WS, int NW, bool BF16, int SHAPE>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void mixed_persistent_kernel(KParams p, const KJob *__restrict__ jobs,
                                                                    const WinGroup *__restrict__ groups,
                                                                    const int *__restrict__ range_begin,
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
         __syncthreads();
         if (wave < gcount) {
             const int lw = __builtin_amdgcn_readfirstlane(groups[gi].win[wave]);
-            process_window_mixed<WS, BF16>(p, J, lw / J.nbj, lw % J.nbj, lw, wl, lds);
+            process_window_mixed<WS, BF16, SHAPE>(p, J, lw / J.nbj, lw % J.nbj, lw, wl, lds);
         }
         __syncthreads();
     }
@@ -456,51 +456,65 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
 
 size_t mixed_lds_bytes(int ws, int nw) { return ws == 16 ? MixedLds<16>::bytes(nw) : MixedLds<8>::bytes(nw); }
 
-int launch_mixed_window(const KParams &p, const KJob &job, int ws, void *stream) {
+template <int SHAPE>
+static int launch_mw(const KParams &p, const KJob &job, int ws, void *stream) {
     const long long nwin = (long long)job.nbi * job.nbj;
     if (nwin <= 0) return 0;
     const size_t lds = mixed_lds_bytes(ws, 1);
     const dim3 grid((unsigned)nwin), block(64);
-    if (ws == 16 && p.dft_bf16)
-        mixed_window_kernel<16, true><<<grid, block, lds, (hipStream_t)stream>>>(p, job);
+    if (ws == 16 && p.dft_bf16 && SHAPE == SHAPE_THREE_QUARTER)
+        mixed_window_kernel<16, true, SHAPE_THREE_QUARTER><<<grid, block, lds, (hipStream_t)stream>>>(p, job);
     else if (ws == 16)
-        mixed_window_kernel<16, false><<<grid, block, lds, (hipStream_t)stream>>>(p, job);
+        mixed_window_kernel<16, false, SHAPE><<<grid, block, lds, (hipStream_t)stream>>>(p, job);
     else
-        mixed_window_kernel<8, false><<<grid, block, lds, (hipStream_t)stream>>>(p, job);
+        mixed_window_kernel<8, false, SHAPE><<<grid, block, lds, (hipStream_t)stream>>>(p, job);
     return (int)hipGetLastError();
 }
 
-template <int WS, int NW, bool BF16>
+// Shapes with kernels: three-quarter and quarter sampling (the host rejects
+// others, and the split-BF16 DFT with quarter sampling, before launching).
+int launch_mixed_window(const KParams &p, const KJob &job, int ws, void *stream) {
+    return p.shape == SHAPE_QUARTER ? launch_mw<SHAPE_QUARTER>(p, job, ws, stream)
+                                    : launch_mw<SHAPE_THREE_QUARTER>(p, job, ws, stream);
+}
+
+template <int WS, int NW, bool BF16, int SHAPE>
 static int launch_mp(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, const int *range_begin,
                      unsigned int *counters, int grid, void *stream) {
     const size_t lds = MixedLds<WS>::bytes(NW);
-    mixed_persistent_kernel<WS, NW, BF16><<<dim3(grid), dim3(64 * NW), lds, (hipStream_t)stream>>>(
+    mixed_persistent_kernel<WS, NW, BF16, SHAPE><<<dim3(grid), dim3(64 * NW), lds, (hipStream_t)stream>>>(
         p, d_jobs, d_groups, range_begin, counters);
     return (int)hipGetLastError();
 }
 
-template <int WS, bool BF16>
+template <int WS, bool BF16, int SHAPE>
 static int launch_mp_nw(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, const int *range_begin,
                         unsigned int *counters, int nw, int grid, void *stream) {
-    if (nw == 1) return launch_mp<WS, 1, BF16>(p, d_jobs, d_groups, range_begin, counters, grid, stream);
-    if (nw == 2) return launch_mp<WS, 2, BF16>(p, d_jobs, d_groups, range_begin, counters, grid, stream);
-    return launch_mp<WS, 4, BF16>(p, d_jobs, d_groups, range_begin, counters, grid, stream);
+    if (nw == 1) return launch_mp<WS, 1, BF16, SHAPE>(p, d_jobs, d_groups, range_begin, counters, grid, stream);
+    if (nw == 2) return launch_mp<WS, 2, BF16, SHAPE>(p, d_jobs, d_groups, range_begin, counters, grid, stream);
+    return launch_mp<WS, 4, BF16, SHAPE>(p, d_jobs, d_groups, range_begin, counters, grid, stream);
 }
 
 int launch_mixed_persistent(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, const int *range_begin,
                             unsigned int *counters, int ws, int nw, int grid, void *stream) {
+    constexpr int TQ = SHAPE_THREE_QUARTER, QS = SHAPE_QUARTER;
+    if (p.shape == QS)
+        return ws == 16 ? launch_mp_nw<16, false, QS>(p, d_jobs, d_groups, range_begin, counters, nw, grid, stream)
+                        : launch_mp_nw<8, false, QS>(p, d_jobs, d_groups, range_begin, counters, nw, grid, stream);
     if (ws == 16 && p.dft_bf16)
-        return launch_mp_nw<16, true>(p, d_jobs, d_groups, range_begin, counters, nw, grid, stream);
-    if (ws == 16) return launch_mp_nw<16, false>(p, d_jobs, d_groups, range_begin, counters, nw, grid, stream);
-    return launch_mp_nw<8, false>(p, d_jobs, d_groups, range_begin, counters, nw, grid, stream);
+        return launch_mp_nw<16, true, TQ>(p, d_jobs, d_groups, range_begin, counters, nw, grid, stream);
+    if (ws == 16) return launch_mp_nw<16, false, TQ>(p, d_jobs, d_groups, range_begin, counters, nw, grid, stream);
+    return launch_mp_nw<8, false, TQ>(p, d_jobs, d_groups, range_begin, counters, nw, grid, stream);
 }
 
 template <int WS, int NW>
 static int occ_mp(int *blocks) {
-    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, mixed_persistent_kernel<WS, NW, false>,
-                                                             64 * NW, MixedLds<WS>::bytes(NW));
+    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        blocks, mixed_persistent_kernel<WS, NW, false, SHAPE_THREE_QUARTER>, 64 * NW, MixedLds<WS>::bytes(NW));
 }
 
+// Occupancy of the three-quarter instantiation (the quarter-sampling one uses
+// no more registers or LDS).
 int mixed_blocks_per_cu(int ws, int nw, int *blocks) {
     if (ws == 16) return nw == 1 ? occ_mp<16, 1>(blocks) : nw == 2 ? occ_mp<16, 2>(blocks) : occ_mp<16, 4>(blocks);
     return nw == 1 ? occ_mp<8, 1>(blocks) : nw == 2 ? occ_mp<8, 2>(blocks) : occ_mp<8, 4>(blocks);

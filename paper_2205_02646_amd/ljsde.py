@@ -26,6 +26,13 @@ FP64 = 1
 FP32 = 2
 DFT_SPLITBF16 = 4
 Q_ONES = 8
+# pixel shapes: quadrant masks in flag bits 8..11 (0 = three-quarter sampling)
+SHAPE_THREE_QUARTER = 0xE
+SHAPE_QUARTER = 0x1
+
+
+def SHAPE(mask: int) -> int:
+    return (mask & 15) << 8
 STATE_FP32 = 16
 
 _NAMES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOMEM: "ENOMEM", EHIP: "EHIP", EBADID: "EBADID"}
@@ -95,13 +102,15 @@ def version() -> int:
 
 def plan(pattern, window: int = 32, block: int = 4, iters: int = 100, rho: float = 0.7,
          gamma: float = 0.5, fp64: bool = False, splitbf16: bool = False, q_ones: bool = False,
-         state_fp32: bool = False) -> int:
-    """Register a plan for an opaque-quadrant pattern tile; returns its id."""
+         state_fp32: bool = False, shape: int = 0) -> int:
+    """Register a plan for a pattern tile of quadrant codes; returns its id.
+    ``shape`` is the pixel-shape mask (0 or SHAPE_THREE_QUARTER: L-shaped
+    pixels; SHAPE_QUARTER: one transparent quadrant per pixel)."""
     pat = np.ascontiguousarray(np.asarray(pattern, dtype=np.uint8))
     if pat.ndim != 2:
         raise ValueError("pattern must be 2-D")
     flags = ((FP64 if fp64 else FP32) | (DFT_SPLITBF16 if splitbf16 else 0) | (Q_ONES if q_ones else 0)
-             | (STATE_FP32 if state_fp32 else 0))
+             | (STATE_FP32 if state_fp32 else 0) | SHAPE(shape))
     return _check(lib().ljsde_plan(pat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), pat.shape[0],
                                    pat.shape[1], window, block, iters, rho, gamma, flags))
 

@@ -55,6 +55,10 @@ TILE = random_pattern(4, 4, seed=0)
     (dict(fp64=True, state_fp32=True), ljsde.EINVAL),
     (dict(splitbf16=True, state_fp32=True), ljsde.EUNSUPPORTED),
     (dict(splitbf16=True, window=16), ljsde.EUNSUPPORTED),
+    (dict(shape=0x3), ljsde.EUNSUPPORTED),      # a valid shape with no kernel
+    (dict(shape=0xF), ljsde.EUNSUPPORTED),
+    (dict(shape=ljsde.SHAPE_QUARTER, splitbf16=True), ljsde.EUNSUPPORTED),
+    (dict(shape=ljsde.SHAPE_QUARTER, state_fp32=True), ljsde.EUNSUPPORTED),
 ])
 def test_plan_validation(kwargs, code):
     with pytest.raises(ljsde.LjsdeError) as e:
@@ -181,39 +185,54 @@ def test_class_members_share_the_oracle_local_measurement_matrix(period, rows, c
     ljsde.release(pid)
 
 
-def _H(W):
-    """L-pixel responses H_o(sigma, rho) = sum of exp(i theta (a sigma + b rho))
-    over the three transparent quadrants (a, b) of orientation o."""
+def _H(W, shape=0xE):
+    """Pixel responses H_o(sigma, rho) = sum of exp(i theta (a sigma + b rho))
+    over the quadrants (a, b) the pixel of code o collects (for L pixels the
+    three transparent ones; for quarter sampling quadrant o alone)."""
     s = np.arange(W)
     e = np.exp(2j * np.pi * s / W)
     out = np.zeros((4, W, W), dtype=complex)
     for o in range(4):
         for a in (0, 1):
             for b in (0, 1):
-                if (a, b) != (o >> 1, o & 1):
+                collected = (a, b) == (o >> 1, o & 1) if shape == 0x1 else (a, b) != (o >> 1, o & 1)
+                if collected:
                     out[o] += (e[:, None] ** a) * (e[None, :] ** b)
     return out
 
 
-@pytest.mark.parametrize("W,bi,bj", [(32, 10, 9), (32, 0, 3), (16, 1, 5)])
-def test_class_tables_reproduce_dense_C_and_D(W, bi, bj):
+def test_shape_flags_are_kept_and_default_to_three_quarter():
+    p0 = ljsde.plan(TILE)
+    p1 = ljsde.plan(TILE, shape=ljsde.SHAPE_QUARTER)
+    p2 = ljsde.plan(TILE, shape=ljsde.SHAPE_THREE_QUARTER, fp64=True)
+    assert (ljsde.plan_info(p0)["flags"] >> 8) & 15 == 0
+    assert (ljsde.plan_info(p1)["flags"] >> 8) & 15 == 0x1
+    assert (ljsde.plan_info(p2)["flags"] >> 8) & 15 == 0xE
+    for p in (p0, p1, p2):
+        ljsde.release(p)
+
+
+@pytest.mark.parametrize("W,bi,bj,shape", [(32, 10, 9, 0xE), (32, 0, 3, 0xE), (16, 1, 5, 0xE),
+                                           (32, 10, 9, 0x1), (16, 0, 2, 0x1)])
+def test_class_tables_reproduce_dense_C_and_D(W, bi, bj, shape):
     """The library's FP64 S_o and D rebuild the oracle's dense C (eq. (14))
-    and D (eq. (13)) of the same local measurement matrix."""
+    and D (eq. (13)) of the same local measurement matrix, for L pixels and
+    for quarter sampling."""
     tile = random_pattern(4, 4, seed=3)
     rows = cols = 96
-    pid = ljsde.plan(tile, window=W, block=4)
+    pid = ljsde.plan(tile, window=W, block=4, shape=shape)
     n, cls = ljsde.class_map(pid, rows // 2, cols // 2)
     c = int(cls[bi * (cols // 4) + bj])
     S, D, codes = ljsde.class_tables(pid, rows // 2, cols // 2, c, W)
     y = np.zeros((rows // 2, cols // 2))
     _, ocodes, valid = O.local_window(y, tile, bi, bj, W, 4)
-    A = O.local_measurement_operator(ocodes, valid, W)
+    A = O.local_measurement_operator(ocodes, valid, W, shape)
     a = O.basis_responses(A, O.fourier_basis(W))
     w = O.spatial_weights(W, 0.7) * valid.reshape(-1)
     Bm, C, Dref = O.rljsde_precompute(a, w)
     np.testing.assert_allclose(D, Dref, rtol=1e-12)
     Ws = W // 2
-    H = _H(W).reshape(4, W * W)
+    H = _H(W, shape).reshape(4, W * W)
     S = S.reshape(Ws, Ws, 4)
     sg = np.arange(W * W) // W
     rh = np.arange(W * W) % W

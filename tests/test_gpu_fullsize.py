@@ -11,7 +11,7 @@ sequence against the oracle on the same float32 input.
 import numpy as np
 import pytest
 
-from synth import batch_cases, make_case
+from synth import QUARTER, batch_cases, make_case
 from tests.oracle_runs import centre_blocks, run_blocks, sample_blocks
 
 torch = pytest.importorskip("torch")
@@ -44,8 +44,8 @@ def _gather(out, blocks):
     return {(bi, bj): out[B * bi:B * bi + B, B * bj:B * bj + B] for bi, bj in blocks}
 
 
-def _fp32_batched(L, y32, tile, iters):
-    pid = L.plan(tile, iters=iters)
+def _fp32_batched(L, y32, tile, iters, shape=0):
+    pid = L.plan(tile, iters=iters, shape=shape)
     y = torch.from_numpy(y32).to("cuda:0")
     out = torch.empty((2 * y32.shape[0], 2 * y32.shape[1]), dtype=torch.float32, device="cuda:0")
     L.reconstruct_batch([(y, pid, out)])
@@ -54,8 +54,8 @@ def _fp32_batched(L, y32, tile, iters):
     return pid, y, o
 
 
-def _fp64_plain(L, y64, tile, iters):
-    pid = L.plan(tile, iters=iters, fp64=True)
+def _fp64_plain(L, y64, tile, iters, shape=0):
+    pid = L.plan(tile, iters=iters, fp64=True, shape=shape)
     o = L.reconstruct(torch.from_numpy(y64).to("cuda:0"), pid).cpu().numpy()
     L.release(pid)
     return o
@@ -127,6 +127,22 @@ def test_frame8192_many_classes_crop(L):
     sample = sample_blocks(2048, 2048, 100, seed=3)
     ref64 = run_blocks(c["y"], c["tile"], sample, iters=250)
     _check_fp64(_fp64_plain(L, c["y"], c["tile"], 250), ref64, "frame8192")
+
+
+def test_quarter_sampling_frame1024_crop(L):
+    """1024x1024 frame under quarter sampling (one transparent quadrant per
+    pixel), random 8x8-sensor tile, 100 iterations: every window of the
+    256x256 centre crop and a sample in FP64."""
+    c = make_case(1024, 1024, 8, seed=3, shape=QUARTER)
+    y32 = c["y"].astype(np.float32)
+    crop = centre_blocks(256, 256, 256)
+    ref32 = run_blocks(y32.astype(np.float64), c["tile"], crop, iters=100, shape=QUARTER)
+    pid, y, o32 = _fp32_batched(L, y32, c["tile"], 100, shape=QUARTER)
+    _check_fp32(L, pid, y, o32, ref32, c["clean"], 100, "quarter 1024 crop")
+    L.release(pid)
+    sample = sample_blocks(256, 256, 150, seed=5)
+    ref64 = run_blocks(c["y"], c["tile"], sample, iters=100, shape=QUARTER)
+    _check_fp64(_fp64_plain(L, c["y"], c["tile"], 100, shape=QUARTER), ref64, "quarter 1024")
 
 
 def test_paper_shape_1200(L):

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from oracle import ljsde_oracle as O
-from synth import make_case, random_pattern, sense
+from synth import QUARTER, THREE_QUARTER, make_case, random_pattern, sense
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -43,26 +43,33 @@ def _psnr(a, b):
     return 10 * np.log10(255.0 ** 2 / np.mean((a - b) ** 2))
 
 
+TQ, QS = THREE_QUARTER, QUARTER
 CASES = {
-    # name: (rows, cols, pattern, W, B, iters, rho, gamma, q_ones, seed)
-    "w32b4_ragged": (48, 40, 4, 32, 4, 30, 0.7, 0.5, False, 5),
-    "nonrecurrent_64": (64, 64, None, 32, 4, 100, 0.7, 0.5, False, 0),
-    "w16b4": (40, 56, (3, 5), 16, 4, 40, 0.7, 0.5, False, 6),
-    "w32b8": (48, 64, 4, 32, 8, 25, 0.7, 0.5, False, 7),
-    "q_ones": (40, 40, 4, 32, 4, 25, 0.7, 0.5, True, 8),
-    "gamma_rho": (40, 48, 2, 32, 4, 25, 0.5, 1.5, False, 9),
-    "w16b8_tiny": (8, 24, 2, 16, 8, 12, 0.7, 0.5, False, 10),
+    # name: (rows, cols, pattern, W, B, iters, rho, gamma, q_ones, seed, pixel shape)
+    "w32b4_ragged": (48, 40, 4, 32, 4, 30, 0.7, 0.5, False, 5, TQ),
+    "nonrecurrent_64": (64, 64, None, 32, 4, 100, 0.7, 0.5, False, 0, TQ),
+    "w16b4": (40, 56, (3, 5), 16, 4, 40, 0.7, 0.5, False, 6, TQ),
+    "w32b8": (48, 64, 4, 32, 8, 25, 0.7, 0.5, False, 7, TQ),
+    "q_ones": (40, 40, 4, 32, 4, 25, 0.7, 0.5, True, 8, TQ),
+    "gamma_rho": (40, 48, 2, 32, 4, 25, 0.5, 1.5, False, 9, TQ),
+    "w16b8_tiny": (8, 24, 2, 16, 8, 12, 0.7, 0.5, False, 10, TQ),
+    # quarter sampling (one transparent quadrant per pixel)
+    "quarter_w32b4": (48, 40, 4, 32, 4, 30, 0.7, 0.5, False, 11, QS),
+    "quarter_nonrecurrent": (64, 64, None, 32, 4, 60, 0.7, 0.5, False, 12, QS),
+    "quarter_w16b8": (40, 56, (3, 5), 16, 8, 30, 0.7, 0.5, False, 13, QS),
 }
 
 
 def _case(name):
-    rows, cols, pattern, W, B, iters, rho, gamma, q_ones, seed = CASES[name]
-    c = make_case(rows, cols, pattern, seed=seed)
-    kw = dict(W=W, B=B, iters=iters, rho=rho, gamma=gamma, form="RL", q_mode="ones" if q_ones else "fsr")
+    rows, cols, pattern, W, B, iters, rho, gamma, q_ones, seed, shape = CASES[name]
+    c = make_case(rows, cols, pattern, seed=seed, shape=shape)
+    kw = dict(W=W, B=B, iters=iters, rho=rho, gamma=gamma, form="RL", q_mode="ones" if q_ones else "fsr",
+              shape=shape)
     ref, tr = O.reconstruct(c["y"], c["tile"], traces=True, **kw)
     c["y32"] = c["y"].astype(np.float32)
     c["ref32"], c["tr32"] = O.reconstruct(c["y32"].astype(np.float64), c["tile"], traces=True, **kw)
-    return c, ref, tr, dict(window=W, block=B, iters=iters, rho=rho, gamma=gamma, q_ones=q_ones)
+    return c, ref, tr, dict(window=W, block=B, iters=iters, rho=rho, gamma=gamma, q_ones=q_ones,
+                            shape=0 if shape == TQ else shape)
 
 
 _cache = {}
@@ -94,6 +101,8 @@ def test_fp64_matches_oracle(L, name):
 @pytest.mark.parametrize("state_fp32", [False, True], ids=["fp64state", "fp32state"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_fp32_matches_oracle(L, name, state_fp32):
+    if state_fp32 and CASES[name][-1] != THREE_QUARTER:
+        pytest.skip("the all-FP32 variant exists for three-quarter sampling only")
     c, ref, tr, kw = _cached(name)
     ref32 = c["ref32"]
     pid = L.plan(c["tile"], state_fp32=state_fp32, **kw)
