@@ -616,9 +616,10 @@ int prepare_batch(const ljsde_job *jobs, int n, void *stream, BatchState **out) 
         if (st) return st;
         if (p->fp64()) return fail(LJSDE_EUNSUPPORTED, "job %d: batched launches need FP32 plans", i);
         if (p->W != p0->W || p->B != p0->B || p->iters != p0->iters || p->gamma != p0->gamma ||
-            p->tau != p0->tau || ((p->flags & LJSDE_STATE_FP32) != 0) != sf32)
+            p->tau != p0->tau || ((p->flags & LJSDE_STATE_FP32) != 0) != sf32 || p->shape != p0->shape ||
+            ((p->flags ^ p0->flags) & LJSDE_DFT_SPLITBF16))
             return fail(LJSDE_EINVAL, "job %d: all plans of a batch need equal window, block, iters, "
-                                      "gamma, energy floor and state precision", i);
+                                      "gamma, energy floor, state precision, DFT mode and pixel shape", i);
         if (!jobs[i].measurements || !jobs[i].out)
             return fail(LJSDE_EINVAL, "job %d: null device pointer", i);
         st = check_size(*p, jobs[i].sensor_rows, jobs[i].sensor_cols);

@@ -242,3 +242,20 @@ def test_class_tables_reproduce_dense_C_and_D(W, bi, bj, shape):
     Cf = sum(np.conj(H[o])[:, None] * H[o][None, :] * S[dk, dl, o] for o in range(4))
     np.testing.assert_allclose(Cf, C, atol=1e-11 * np.abs(C).max())
     ljsde.release(pid)
+
+
+@pytest.mark.parametrize("other", [dict(shape=ljsde.SHAPE_QUARTER), dict(splitbf16=True), dict(iters=11)])
+def test_batch_rejects_plans_that_need_another_kernel(other):
+    """All plans of one batched launch run in one kernel instantiation, so a
+    batch that mixes pixel shapes, DFT modes or iteration counts is refused on
+    the host (before any device work)."""
+    base = dict(iters=10)
+    p0 = ljsde.plan(TILE, **base)
+    p1 = ljsde.plan(TILE, **{**base, **other})
+    buf = (ctypes.c_float * 64)()
+    addr = ctypes.cast(buf, ctypes.c_void_p).value
+    jobs = (ljsde.Job * 2)(ljsde.Job(addr, 4, 4, p0, addr), ljsde.Job(addr, 4, 4, p1, addr))
+    st = ljsde.lib().ljsde_reconstruct_batch(jobs, 2, None)
+    assert st == ljsde.EINVAL and "job 1" in ljsde.last_error()
+    ljsde.release(p0)
+    ljsde.release(p1)
