@@ -58,9 +58,16 @@ enum {
                                  error ~2^-16 in the initial state; selections can then
                                  diverge from FP64 at near ties) */
     LJSDE_Q_ONES = 8,         /* frequency weight q = 1 (test mode) */
-    LJSDE_STATE_FP32 = 16     /* FP32 plans: keep the loop state and its updates in FP32 too
+    LJSDE_STATE_FP32 = 16,    /* FP32 plans: keep the loop state and its updates in FP32 too
                                  (no FP64 re-decision); greedy selections can then diverge
                                  from FP64 at near ties */
+    LJSDE_DENSE_C = 32        /* FP64 plans: the dense form of Sec. IV. Per class the full
+                                 W^2 x W^2 matrix C of eq. (14) is built in device memory
+                                 (16 MiB per class at W = 32, on the first reconstruction of an
+                                 image size; LJSDE_ENOMEM if it does not fit), each window
+                                 keeps R of eq. (12) for all W^2 frequencies and subtracts a
+                                 column of C per iteration (eq. (17)). Same results as the
+                                 factorised FP64 path; single-image calls only */
 };
 
 /*

@@ -1,0 +1,236 @@
+// RL-JSDE in its dense form (Sec. IV, eqs. (11)-(18)) on gfx950.
+//
+// Per class (local measurement matrix), the full W^2 x W^2 matrix C of
+// eq. (14) sits in device memory, FP64. A window keeps the projected residual
+// R(sigma, rho) of all W^2 frequencies as its state (eq. (12) at r = y); every
+// iteration selects by eq. (11), steps by eqs. (15)-(16) and subtracts
+// gamma * delta times column (u, v) of C (eq. (17)). Per window-iteration the
+// work is one metric per frequency and one complex multiply-add per
+// frequency, and the column read is W^2 * 16 bytes (16 KiB at W = 32): the
+// iteration is bound by the bandwidth of the cache level that holds C, not by
+// the VALU.
+//
+// C is built on the device from the factorised class tables,
+// C(f, g) = sum_o conj(H_o(f)) H_o(g) S_o(f - g) (the same matrix as eq. (14),
+// see ljsde_kernels.hip), and stored so that a wavefront's read of one column
+// is 16 loads of 64 consecutive complex values.
+#include <hip/hip_runtime.h>
+
+#include "ljsde_device.h"
+#include "ljsde_internal.h"
+#include "ljsde_window.h"
+
+namespace ljsde {
+
+// Frequency sigma * W + rho of entry (t, c) of lane L: position
+// (k, l) = (L / WS + (64 / WS) t, L % WS), c = 2a + b for (k + WS a, l + WS b).
+template <int WS>
+__device__ __forceinline__ int dense_freq(int L, int t, int c) {
+    constexpr int W = 2 * WS, KSTEP = 64 / WS;
+    return (L / WS + KSTEP * t + WS * (c >> 1)) * W + L % WS + WS * (c & 1);
+}
+
+// Column g of C for every class of a size set: out[(cls * W^2 + g) * W^2 + e]
+// with e = (4 t + c) * 64 + L the lane-ordered entry of frequency
+// dense_freq(L, t, c). Grid (W^2 columns, classes), 256 threads.
+template <int WS>
+__global__ __launch_bounds__(256) void dense_c_build_kernel(KParams p, const unsigned char *tables, double2 *out) {
+    constexpr int W = 2 * WS, NF = W * W;
+    const int g = blockIdx.x;
+    const int cls = blockIdx.y;
+    const double *S = (const double *)(tables + (size_t)cls * p.lay.stride + p.lay.offS);
+    const double *H = p.c.H;
+    const int kg = (g / W) & (WS - 1), lg = (g % W) & (WS - 1);
+    double Hgr[4], Hgi[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        Hgr[o] = H[((size_t)g * 4 + o) * 2];
+        Hgi[o] = H[((size_t)g * 4 + o) * 2 + 1];
+    }
+    double2 *col = out + ((size_t)cls * NF + g) * NF;
+    for (int e = threadIdx.x; e < NF; e += blockDim.x) {
+        const int L = e & 63, tc = e >> 6;
+        const int f = dense_freq<WS>(L, tc >> 2, tc & 3);
+        const int kf = (f / W) & (WS - 1), lf = (f % W) & (WS - 1);
+        const int pos = ((kf - kg) & (WS - 1)) * WS + ((lf - lg) & (WS - 1));
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const double hr = H[((size_t)f * 4 + o) * 2], hi = H[((size_t)f * 4 + o) * 2 + 1];
+            // conj(H_o(f)) H_o(g)
+            const double ar = hr * Hgr[o] + hi * Hgi[o], ai = hr * Hgi[o] - hi * Hgr[o];
+            const double sr = S[(pos * 4 + o) * 2], si = S[(pos * 4 + o) * 2 + 1];
+            re += ar * sr - ai * si;
+            im += ar * si + ai * sr;
+        }
+        col[e] = make_double2(re, im);
+    }
+}
+
+// LDS of one wavefront: w*y [NPOS] FP64, codes [NPOS], and the VALU DFT's
+// stage [NPOS][4] complex for WS = 8 only
+template <int WS>
+struct DenseLds {
+    static constexpr int NPOS = WS * WS;
+    static constexpr size_t stage = WS == 16 ? 0 : (size_t)NPOS * 8 * 8;
+    static constexpr size_t bytes = stage + (size_t)NPOS * 8 + NPOS;
+};
+
+// One wavefront per window.
+template <int WS, int SHAPE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void dense_kernel(
+    KParams p, KJob j, const double2 *__restrict__ Cd) {
+    extern __shared__ __align__(16) char lds[];
+    constexpr int W = 2 * WS, NF = W * W, NPOS = WS * WS, QPL = NPOS / 64, KSTEP = 64 / WS;
+    const long long w = blockIdx.x;
+    const long long nwin = (long long)j.nbi * j.nbj;
+    if (w >= nwin) return;
+    const int bi = (int)(w / j.nbj), bj = (int)(w % j.nbj);
+    const int lane = threadIdx.x & 63;
+    const int lam = lane % WS, krow = lane / WS;
+
+    const int cls = __builtin_amdgcn_readfirstlane(j.rowcls[bi] * j.ncolk + j.colcls[bj]);
+    const unsigned char *tb = j.tables + (size_t)cls * p.lay.stride;
+    const double *qD64 = (const double *)(tb + p.lay.offQD64);
+    const double *invD = (const double *)(tb + p.lay.offInvD);
+    const signed char *codes = (const signed char *)(tb + p.lay.offCodes);
+
+    using LL = DenseLds<WS>;
+    double *ldsS = (double *)lds;
+    double *ldsX = (double *)(lds + LL::stage);
+    signed char *ldsC = (signed char *)(lds + LL::stage + (size_t)NPOS * 8);
+    C2<double> P[QPL][4];
+    const double e0 = window_prologue<double, WS>(p, j, bi, bj, codes, ldsX, ldsC, ldsS, P);
+
+    // R(0) of eq. (12) through the factorised projection, and q / D
+    const double *ew = p.c.ew;
+    const C2<double> tl = {ew[2 * lam], -ew[2 * lam + 1]};
+    C2<double> R[QPL][4];
+    double qd[QPL][4];
+#pragma unroll
+    for (int t = 0; t < QPL; ++t) {
+        const int kap = krow + KSTEP * t;
+        const C2<double> tk = {ew[2 * kap], -ew[2 * kap + 1]};
+        const C2<double> tkl = {ew[2 * (kap + lam)], -ew[2 * (kap + lam) + 1]};
+        project4<double, SHAPE>(P[t], tl, tk, tkl, R[t]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) qd[t][c] = qD64[dense_freq<WS>(lane, t, c)];
+    }
+
+    const double2 *Cc = Cd + (size_t)cls * NF * NF;
+    const int BB = p.B * p.B;
+    const int oi = lane / p.B, oj = lane % p.B;
+    double outacc = 0.0;
+    double E = e0;
+    int nu_done = 0;
+
+#pragma unroll 1
+    for (int nu = 0; nu < p.iters; ++nu) {
+        // eq. (11): q |R|^2 / D, first maximum in sigma * W + rho order (ties
+        // within TIE_REL go to the lowest index). a = 0 and a = 1 frequencies
+        // are kept apart: all a = 1 indices exceed all a = 0 ones.
+        double best0 = -1.0, best1 = -1.0;
+        int code0 = 0, code1 = 0;
+#pragma unroll
+        for (int t = 0; t < QPL; ++t) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double m = (R[t][c].re * R[t][c].re + R[t][c].im * R[t][c].im) * qd[t][c];
+                if (c < 2) tie_keep<double>(best0, code0, m, 4 * t + c, TIE_REL);
+                else tie_keep<double>(best1, code1, m, 4 * t + c, TIE_REL);
+            }
+        }
+        double best = best0;
+        int idx = dense_freq<WS>(lane, code0 >> 2, code0 & 3);
+        tie_merge<double>(best, idx, best1, dense_freq<WS>(lane, code1 >> 2, code1 & 3), TIE_REL);
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o);
+            const int oid = __shfl_xor(idx, o);
+            tie_merge<double>(best, idx, ob, oid, TIE_REL);
+        }
+        idx = __builtin_amdgcn_readfirstlane(idx);
+        const int u = idx / W, v = idx % W;
+
+        // R_uv from its owner lane
+        const int ku = u % WS, lv = v % WS;
+        const int tu = ku / KSTEP, cu = 2 * (u / WS) + v / WS;
+        const int owner = (ku % KSTEP) * WS + lv;
+        double rr = 0.0, ri = 0.0;
+#pragma unroll
+        for (int t = 0; t < QPL; ++t)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (tu == t && cu == c) {
+                    rr = R[t][c].re;
+                    ri = R[t][c].im;
+                }
+        rr = readlane_f64(rr, owner);
+        ri = readlane_f64(ri, owner);
+
+        // eqs. (15)-(16) and the energy of eq. (8)
+        const double id = invD[idx];
+        const double gr = p.gamma * rr * id, gi = p.gamma * ri * id;
+        E = uniform_f64(E - p.ecoef * (rr * rr + ri * ri) * id);
+        // eq. (18) on the central block, pick by pick
+        if (lane < BB) {
+            const int ph = ((p.off + oi) * u + (p.off + oj) * v) & (W - 1);
+            outacc += gr * ew[2 * ph] - gi * ew[2 * ph + 1];
+        }
+        if (j.sel != nullptr && lane == 0) j.sel[w * p.iters + nu] = (int16_t)idx;
+        nu_done = nu + 1;
+        if (p.tau > 0.0 && E <= p.tau * e0) break;
+
+        // eq. (17): R -= gamma delta C(:, (u, v))
+        const double2 *col = Cc + (size_t)idx * NF + lane;
+#pragma unroll
+        for (int t = 0; t < QPL; ++t)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double2 cv = col[(4 * t + c) * 64];
+                R[t][c].re -= gr * cv.x - gi * cv.y;
+                R[t][c].im -= gr * cv.y + gi * cv.x;
+            }
+    }
+    if (j.sel != nullptr)
+        for (int nu = nu_done + lane; nu < p.iters; nu += 64) j.sel[w * p.iters + nu] = -1;
+    if (lane < BB) {
+        double *O = (double *)j.out;
+        const size_t row = (size_t)(p.B * bi + oi);
+        O[row * (size_t)(2 * j.Ns) + (size_t)(p.B * bj + oj)] = outacc;
+    }
+}
+
+size_t dense_c_bytes(int ws, int n_classes) {
+    const size_t nf = (size_t)(2 * ws) * (2 * ws);
+    return (size_t)n_classes * nf * nf * sizeof(double2);
+}
+
+int launch_dense_c_build(const KParams &p, const unsigned char *tables, int n_classes, int ws, void *out,
+                         void *stream) {
+    if (n_classes <= 0) return 0;
+    const int nf = (2 * ws) * (2 * ws);
+    const dim3 grid((unsigned)nf, (unsigned)n_classes);
+    if (ws == 16)
+        dense_c_build_kernel<16><<<grid, dim3(256), 0, (hipStream_t)stream>>>(p, tables, (double2 *)out);
+    else
+        dense_c_build_kernel<8><<<grid, dim3(256), 0, (hipStream_t)stream>>>(p, tables, (double2 *)out);
+    return (int)hipGetLastError();
+}
+
+template <int WS, int SHAPE>
+static int launch_dense_t(const KParams &p, const KJob &job, const void *C, void *stream) {
+    const long long nwin = (long long)job.nbi * job.nbj;
+    if (nwin <= 0) return 0;
+    dense_kernel<WS, SHAPE><<<dim3((unsigned)nwin), dim3(64), DenseLds<WS>::bytes, (hipStream_t)stream>>>(
+        p, job, (const double2 *)C);
+    return (int)hipGetLastError();
+}
+
+int launch_dense(const KParams &p, const KJob &job, const void *C, int ws, void *stream) {
+    constexpr int TQ = SHAPE_THREE_QUARTER, QS = SHAPE_QUARTER;
+    if (p.shape == QS)
+        return ws == 16 ? launch_dense_t<16, QS>(p, job, C, stream) : launch_dense_t<8, QS>(p, job, C, stream);
+    return ws == 16 ? launch_dense_t<16, TQ>(p, job, C, stream) : launch_dense_t<8, TQ>(p, job, C, stream);
+}
+
+}  // namespace ljsde

@@ -88,6 +88,7 @@ struct SizeSet {
     unsigned char *d_tables = nullptr;
     int *d_rowcls = nullptr;
     int *d_colcls = nullptr;
+    void *d_dense = nullptr;  // dense C of every class (LJSDE_DENSE_C plans), built on first use
 };
 
 struct Plan {
@@ -777,12 +778,14 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, i
     if (!(rho > 0.0 && rho <= 1.0)) return fail(LJSDE_EINVAL, "rho %g must be in (0, 1]", rho);
     if (!(gamma > 0.0 && gamma < 2.0)) return fail(LJSDE_EINVAL, "gamma %g must be in (0, 2)", gamma);
     const unsigned known = LJSDE_FP64 | LJSDE_FP32 | LJSDE_DFT_SPLITBF16 | LJSDE_Q_ONES | LJSDE_STATE_FP32 |
-                           LJSDE_SHAPE(15);
+                           LJSDE_DENSE_C | LJSDE_SHAPE(15);
     if (flags & ~known) return fail(LJSDE_EINVAL, "unknown flags 0x%x", flags & ~known);
     if (((flags & LJSDE_FP64) != 0) == ((flags & LJSDE_FP32) != 0))
         return fail(LJSDE_EINVAL, "exactly one of LJSDE_FP64 / LJSDE_FP32 is required");
     if ((flags & (LJSDE_DFT_SPLITBF16 | LJSDE_STATE_FP32)) && (flags & LJSDE_FP64))
         return fail(LJSDE_EINVAL, "LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32 apply to FP32 plans only");
+    if ((flags & LJSDE_DENSE_C) && !(flags & LJSDE_FP64))
+        return fail(LJSDE_EINVAL, "LJSDE_DENSE_C applies to FP64 plans only");
     if (!(window == 32 || window == 16))
         return fail(LJSDE_EUNSUPPORTED, "no kernel for window %d (have 16, 32)", window);
     if ((flags & LJSDE_DFT_SPLITBF16) && ((flags & LJSDE_STATE_FP32) || window != 32))
@@ -827,6 +830,24 @@ int ljsde_set_energy_floor(int pattern_id, double tau) {
     return ok();
 }
 
+// Dense C of every class of a size set (eq. (14), FP64), built on the device
+// from the class tables on first use; refused with LJSDE_ENOMEM when it would
+// not fit in the free device memory with 1 GiB to spare.
+static int ensure_dense(Plan &p, SizeSet &s, void *stream) {
+    if (s.d_dense) return LJSDE_OK;
+    const size_t bytes = dense_c_bytes(p.Ws, s.n_classes());
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    if (bytes + (1ull << 30) > free_b)
+        return fail(LJSDE_ENOMEM, "dense C needs %.1f GiB for %d classes, %.1f GiB free", bytes / 1073741824.0,
+                    s.n_classes(), free_b / 1073741824.0);
+    int st = dev_alloc(&s.d_dense, bytes);
+    if (st) return st;
+    const int e = launch_dense_c_build(make_params(p), s.d_tables, s.n_classes(), p.Ws, s.d_dense, stream);
+    if (e) return fail(LJSDE_EHIP, "dense C build: %s", hipGetErrorString((hipError_t)e));
+    return LJSDE_OK;
+}
+
 static int reconstruct_impl(const void *y, int Ms, int Ns, int id, void *out, int16_t *sel, void *stream) {
     std::lock_guard<std::mutex> lk(g_mu);
     Plan *p = nullptr;
@@ -841,7 +862,11 @@ static int reconstruct_impl(const void *y, int Ms, int Ns, int id, void *out, in
     KParams k = make_params(*p);
     KJob j = make_job(*s, y, out, sel, 0);
     int e = 0;
-    if (p->fp64()) {
+    if (p->flags & LJSDE_DENSE_C) {
+        st = ensure_dense(*p, *s, stream);
+        if (st) return st;
+        e = launch_dense(k, j, s->d_dense, p->Ws, stream);
+    } else if (p->fp64()) {
         e = launch_plain_f64(k, j, p->Ws, stream);
     } else if (sel) {
         e = (p->flags & LJSDE_STATE_FP32) ? launch_plain_f32(k, j, p->Ws, stream)
@@ -958,6 +983,7 @@ int ljsde_release(int pattern_id) {
         if (s.d_tables) (void)hipFree(s.d_tables);
         if (s.d_rowcls) (void)hipFree(s.d_rowcls);
         if (s.d_colcls) (void)hipFree(s.d_colcls);
+        if (s.d_dense) (void)hipFree(s.d_dense);
     }
     if (p->d_consts) (void)hipFree(p->d_consts);
     g_plans[pattern_id].reset();

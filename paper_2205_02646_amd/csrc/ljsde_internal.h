@@ -78,6 +78,12 @@ constexpr int XCD_RANGES = COUNTERS;
 int launch_mixed_persistent(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, const int *range_begin,
                             unsigned int *counters, int ws, int nw, int grid, void *stream);
 int mixed_blocks_per_cu(int ws, int nw, int *blocks);
+// Dense form (ljsde_dense.hip): bytes of the dense C of n classes, its build
+// from the class tables, and the one-wavefront-per-window FP64 launch.
+size_t dense_c_bytes(int ws, int n_classes);
+int launch_dense_c_build(const KParams &p, const unsigned char *tables, int n_classes, int ws, void *out,
+                         void *stream);
+int launch_dense(const KParams &p, const KJob &job, const void *C, int ws, void *stream);
 size_t mixed_lds_bytes(int ws, int nw);
 
 }  // namespace ljsde

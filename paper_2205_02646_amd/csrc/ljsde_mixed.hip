@@ -48,26 +48,6 @@ struct MixedLds {
     static constexpr size_t bytes(int nw) { return shared_bytes + nw * wave_bytes; }
 };
 
-// R(a, b) for the four frequencies (k + Ws a, l + Ws b) of one position:
-// R = sum_q (-1)^(qa a + qb b) e^{-i theta (qa k + qb l)} Q_q, with the
-// per-quadrant sums Q_q of the pixel shape (sum_o P_o - P_q for the L pixels
-// of three-quarter sampling).
-template <typename T, int SHAPE>
-__device__ __forceinline__ void project4(const C2<T> P[4], C2<T> tl, C2<T> tk, C2<T> tkl, C2<T> R[4]) {
-    C2<T> Q[4];
-    shape_sums<SHAPE, T>(P, Q);
-    const C2<T> q0 = Q[0], q1 = Q[1], q2 = Q[2], q3 = Q[3];
-    const C2<T> u1 = {tl.re * q1.re - tl.im * q1.im, tl.re * q1.im + tl.im * q1.re};
-    const C2<T> u2 = {tk.re * q2.re - tk.im * q2.im, tk.re * q2.im + tk.im * q2.re};
-    const C2<T> u3 = {tkl.re * q3.re - tkl.im * q3.im, tkl.re * q3.im + tkl.im * q3.re};
-    const C2<T> s1 = {q0.re + u3.re, q0.im + u3.im}, d1 = {q0.re - u3.re, q0.im - u3.im};
-    const C2<T> s2 = {u1.re + u2.re, u1.im + u2.im}, d2 = {u1.re - u2.re, u1.im - u2.im};
-    R[0] = {s1.re + s2.re, s1.im + s2.im};  // (a, b) = (0, 0)
-    R[1] = {d1.re - d2.re, d1.im - d2.im};  // (0, 1)
-    R[2] = {d1.re + d2.re, d1.im + d2.im};  // (1, 0)
-    R[3] = {s1.re - s2.re, s1.im - s2.im};  // (1, 1)
-}
-
 template <int WS, bool BF16, int SHAPE>
 __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJob &j, int bi, int bj,
                                                      long long win_local, char *wlds, const char *glds) {

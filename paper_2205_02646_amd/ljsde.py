@@ -34,6 +34,7 @@ SHAPE_QUARTER = 0x1
 def SHAPE(mask: int) -> int:
     return (mask & 15) << 8
 STATE_FP32 = 16
+DENSE_C = 32
 
 _NAMES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOMEM: "ENOMEM", EHIP: "EHIP", EBADID: "EBADID"}
 
@@ -102,15 +103,17 @@ def version() -> int:
 
 def plan(pattern, window: int = 32, block: int = 4, iters: int = 100, rho: float = 0.7,
          gamma: float = 0.5, fp64: bool = False, splitbf16: bool = False, q_ones: bool = False,
-         state_fp32: bool = False, shape: int = 0) -> int:
+         state_fp32: bool = False, shape: int = 0, dense_c: bool = False) -> int:
     """Register a plan for a pattern tile of quadrant codes; returns its id.
     ``shape`` is the pixel-shape mask (0 or SHAPE_THREE_QUARTER: L-shaped
-    pixels; SHAPE_QUARTER: one transparent quadrant per pixel)."""
+    pixels; SHAPE_QUARTER: one transparent quadrant per pixel). ``dense_c``
+    (FP64 plans) selects the dense form: per class the full C of eq. (14) in
+    device memory, R as the loop state."""
     pat = np.ascontiguousarray(np.asarray(pattern, dtype=np.uint8))
     if pat.ndim != 2:
         raise ValueError("pattern must be 2-D")
     flags = ((FP64 if fp64 else FP32) | (DFT_SPLITBF16 if splitbf16 else 0) | (Q_ONES if q_ones else 0)
-             | (STATE_FP32 if state_fp32 else 0) | SHAPE(shape))
+             | (STATE_FP32 if state_fp32 else 0) | (DENSE_C if dense_c else 0) | SHAPE(shape))
     return _check(lib().ljsde_plan(pat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), pat.shape[0],
                                    pat.shape[1], window, block, iters, rho, gamma, flags))
 

@@ -55,6 +55,7 @@ TILE = random_pattern(4, 4, seed=0)
     (dict(fp64=True, state_fp32=True), ljsde.EINVAL),
     (dict(splitbf16=True, state_fp32=True), ljsde.EUNSUPPORTED),
     (dict(splitbf16=True, window=16), ljsde.EUNSUPPORTED),
+    (dict(dense_c=True), ljsde.EINVAL),          # the dense form exists for FP64 plans
     (dict(shape=0x3), ljsde.EUNSUPPORTED),      # a valid shape with no kernel
     (dict(shape=0xF), ljsde.EUNSUPPORTED),
     (dict(shape=ljsde.SHAPE_QUARTER, splitbf16=True), ljsde.EUNSUPPORTED),

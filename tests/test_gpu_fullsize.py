@@ -99,6 +99,28 @@ def test_frame512_whole(L):
     _check_fp64(_fp64_plain(L, c["y"], c["tile"], 100), ref64, "frame512")
 
 
+def test_frame512_dense_form_equals_factorised_form(L):
+    """The dense form (per-class C of eq. (14), 100 classes) against the
+    factorised FP64 path on every window of the 512x512 frame (same selection
+    sequences, outputs within the FP64 bar), and against the oracle on a
+    sample."""
+    c = make_case(512, 512, 4, seed=0)
+    y = torch.from_numpy(c["y"]).to("cuda:0")
+    pf = L.plan(c["tile"], iters=100, fp64=True)
+    pd = L.plan(c["tile"], iters=100, fp64=True, dense_c=True)
+    of, sf = L.reconstruct_diag(y, pf)
+    od, sd = L.reconstruct_diag(y, pd)
+    err = float(torch.max(torch.abs(of - od)))
+    same = bool(torch.equal(sf, sd))
+    print(f"frame512 dense vs factorised: max-abs {err:.3e}, equal sequences {same}", flush=True)
+    assert err <= FP64_TOL and same
+    sample = sample_blocks(128, 128, 200, seed=6)
+    ref64 = run_blocks(c["y"], c["tile"], sample, iters=100)
+    _check_fp64(od.cpu().numpy(), ref64, "frame512 dense")
+    L.release(pf)
+    L.release(pd)
+
+
 def test_frame2048_noisy_crop(L):
     """2048x2048 frame with N(0, 2^2) noise, random 8x8-sensor tile, 250 iterations."""
     c = make_case(2048, 2048, 8, seed=0, noise=2.0)

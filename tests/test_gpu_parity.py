@@ -81,15 +81,18 @@ def _cached(name):
     return _cache[name]
 
 
+@pytest.mark.parametrize("dense", [False, True], ids=["factorised", "denseC"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_fp64_matches_oracle(L, name):
+def test_fp64_matches_oracle(L, name, dense):
+    """FP64 plans, in the factorised form and in the dense form (per-class C
+    of eq. (14) in device memory, R as the state)."""
     c, ref, tr, kw = _cached(name)
-    pid = L.plan(c["tile"], fp64=True, **kw)
+    pid = L.plan(c["tile"], fp64=True, dense_c=dense, **kw)
     out, sel = L.reconstruct_diag(_dev(c["y"], np.float64), pid)
     out = out.cpu().numpy()
     sel = sel.cpu().numpy()
     err = np.max(np.abs(out - ref))
-    print(f"{name}: FP64 max-abs {err:.3e}")
+    print(f"{name}: FP64 {'dense C' if dense else 'factorised'} max-abs {err:.3e}")
     assert err <= FP64_TOL
     W = kw["window"]
     nbj = out.shape[1] // kw["block"]
