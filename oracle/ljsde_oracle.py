@@ -28,7 +28,11 @@ the mask. Three-quarter sampling, the paper's layout, is ``THREE_QUARTER =
 0b1110`` (all quadrants but o, so the code names the opaque quadrant); quarter
 sampling (Sec. I: one transparent quadrant per pixel) is ``QUARTER = 0b0001``
 (the code names the transparent quadrant). RL-JSDE applies to any such
-periodically repeating layout (Sec. I).
+periodically repeating layout (Sec. I). The most general layout of this
+sensor family (eq. (1) with 2x2 footprints) gives every pixel of the period
+tile its own weight on each quadrant: ``weights[i, j, q]`` multiplies
+quadrant q = 2a + b of the footprint of the pixel at tile position (i, j);
+``reconstruct(..., weights=...)`` takes such a tile instead of codes.
 
 Readings where the paper is silent or garbled (each is listed with its reason
 in the design notes of the repository):
@@ -77,6 +81,7 @@ __all__ = [
     "window_sensor_origin",
     "local_window",
     "local_measurement_operator",
+    "local_measurement_operator_weights",
     "fourier_basis",
     "spatial_weights",
     "frequency_weights",
@@ -87,6 +92,7 @@ __all__ = [
     "synthesize_block",
     "reconstruct",
     "measure_dense",
+    "measure_dense_weights",
     "WindowTrace",
 ]
 
@@ -136,12 +142,15 @@ def local_window(y: np.ndarray, tile: np.ndarray, bi: int, bj: int, W: int, B: i
     """
     Ws = W // 2
     Ms, Ns = y.shape
-    pr, pc = tile.shape
+    pr, pc = tile.shape[:2]
     rs, cs = window_sensor_origin(bi, bj, W, B)
     ii = rs + np.arange(Ws)
     jj = cs + np.arange(Ws)
     valid = ((ii >= 0) & (ii < Ms))[:, None] & ((jj >= 0) & (jj < Ns))[None, :]
-    codes = tile[ii[:, None] % pr, jj[None, :] % pc].astype(np.int64)
+    codes = tile[ii[:, None] % pr, jj[None, :] % pc]
+    # a code tile gives integer codes; a weight tile [pr, pc, 4] gives the
+    # window's per-pixel quadrant weights [W/2, W/2, 4]
+    codes = codes.astype(np.int64) if tile.ndim == 2 else codes.astype(np.float64)
     y_loc = np.zeros((Ws, Ws), dtype=np.float64)
     iv = np.clip(ii, 0, Ms - 1)
     jv = np.clip(jj, 0, Ns - 1)
@@ -171,6 +180,24 @@ def local_measurement_operator(codes: np.ndarray, valid: np.ndarray, W: int,
                 for b in (0, 1):
                     if _integrates(o, a, b, shape):
                         A[m, 2 * ip + a, 2 * jp + b] = 1.0
+    return A
+
+
+def local_measurement_operator_weights(weights: np.ndarray, valid: np.ndarray, W: int) -> np.ndarray:
+    """A^local[m, eta, gamma] of eq. (4) for a general 2x2-footprint layout:
+    sensor pixel m = (W/2) i' + j' weighs quadrant q = 2a + b of its footprint
+    (row 2i' + a, column 2j' + b of the window) by ``weights[i', j', q]``;
+    absent pixels have an all-zero row."""
+    Ws = W // 2
+    A = np.zeros((Ws * Ws, W, W), dtype=np.float64)
+    for ip in range(Ws):
+        for jp in range(Ws):
+            if not valid[ip, jp]:
+                continue
+            m = ip * Ws + jp
+            for a in (0, 1):
+                for b in (0, 1):
+                    A[m, 2 * ip + a, 2 * jp + b] = weights[ip, jp, 2 * a + b]
     return A
 
 
@@ -337,7 +364,10 @@ class _Cache:
         key = (codes.tobytes(), valid.tobytes())
         hit = self.store.get(key)
         if hit is None:
-            A = local_measurement_operator(codes, valid, self.W, self.shape)
+            if codes.ndim == 3:
+                A = local_measurement_operator_weights(codes, valid, self.W)
+            else:
+                A = local_measurement_operator(codes, valid, self.W, self.shape)
             a = basis_responses(A, self.Phi)
             w = self.w_full * valid.reshape(-1)
             if self.form == "RL":
@@ -349,17 +379,23 @@ class _Cache:
 
 
 def reconstruct(y, tile, W=32, B=4, iters=100, rho=0.7, gamma=0.5, form="L",
-                q_mode="fsr", blocks=None, traces=False, shape=THREE_QUARTER):
+                q_mode="fsr", blocks=None, traces=False, shape=THREE_QUARTER, weights=None):
     """Reconstruct the 2x-resolution image from sensor read-out ``y``.
 
     ``tile`` is the pattern tile of quadrant codes (sensor pixel (i, j) uses
-    ``tile[i % pr, j % pc]``); ``shape`` the pixel shape (module docstring). ``form`` is ``"L"`` (L-JSDE) or ``"RL"``
+    ``tile[i % pr, j % pc]``); ``shape`` the pixel shape (module docstring).
+    ``weights`` (a [pr, pc, 4] tile of per-pixel quadrant weights) replaces
+    ``tile`` and ``shape`` for a general layout. ``form`` is ``"L"`` (L-JSDE) or ``"RL"``
     (RL-JSDE, per-class B, C, D cached by the content of the local measurement
     matrix). ``blocks`` restricts the work to a list of (bi, bj) target
     blocks; other output pixels are NaN. Returns the image, and with
     ``traces=True`` also a dict {(bi, bj): WindowTrace}.
     """
     _check_geometry(W, B)
+    if weights is not None:
+        tile = np.asarray(weights, dtype=np.float64)
+        if tile.ndim != 3 or tile.shape[2] != 4:
+            raise ValueError("weights must be a [rows, cols, 4] tile")
     y = np.asarray(y, dtype=np.float64)
     Ms, Ns = y.shape
     M, N = 2 * Ms, 2 * Ns
@@ -385,6 +421,22 @@ def reconstruct(y, tile, W=32, B=4, iters=100, rho=0.7, gamma=0.5, form="L",
         if traces:
             all_traces[(bi, bj)] = tr
     return (out, all_traces) if traces else out
+
+
+def measure_dense_weights(f: np.ndarray, weights: np.ndarray) -> np.ndarray:
+    """eq. (1) for a general layout with an explicitly built global
+    measurement matrix (tiny images only): y_i = sum A_i f with the pixel at
+    tile position (i % pr, j % pc) weighing quadrant q by weights[..., q]."""
+    M, N = f.shape
+    Ms, Ns = M // 2, N // 2
+    pr, pc = weights.shape[:2]
+    A = np.zeros((Ms * Ns, M, N))
+    for i in range(Ms):
+        for j in range(Ns):
+            for a in (0, 1):
+                for b in (0, 1):
+                    A[i * Ns + j, 2 * i + a, 2 * j + b] = weights[i % pr, j % pc, 2 * a + b]
+    return np.tensordot(A, f, axes=([1, 2], [0, 1])).reshape(Ms, Ns)
 
 
 def measure_dense(f: np.ndarray, tile: np.ndarray, shape: int = THREE_QUARTER) -> np.ndarray:

@@ -40,6 +40,9 @@ __all__ = [
     "batch_cases",
     "THREE_QUARTER",
     "QUARTER",
+    "sense_weights",
+    "random_weights",
+    "shape_weights",
 ]
 
 THREE_QUARTER = 0b1110
@@ -150,6 +153,35 @@ def sense(image: np.ndarray, tile: np.ndarray, shape: int = THREE_QUARTER) -> np
             q = codes.astype(np.intp) ^ d
             out = out + quads[ii, jj, q >> 1, q & 1]
     return out
+
+
+def sense_weights(image: np.ndarray, weights: np.ndarray) -> np.ndarray:
+    """Read-out of a general 2x2-footprint sensor: the pixel at tile position
+    (i % pr, j % pc) weighs quadrant q = 2a + b of ``image[2i:2i+2, 2j:2j+2]``
+    by ``weights[i % pr, j % pc, q]``."""
+    rows, cols = image.shape
+    sr, sc = rows // 2, cols // 2
+    pr, pc = weights.shape[:2]
+    quads = image.reshape(sr, 2, sc, 2).transpose(0, 2, 1, 3).reshape(sr, sc, 4)
+    wt = weights[np.arange(sr)[:, None] % pr, np.arange(sc)[None, :] % pc]
+    return np.einsum("ijq,ijq->ij", wt, quads)
+
+
+def random_weights(pat_rows: int, pat_cols: int, seed: int = 0) -> np.ndarray:
+    """A general layout: every tile pixel weighs each quadrant by U(0, 1)
+    (partially transparent masks), with one quadrant of every pixel at most
+    0.1 (mostly opaque)."""
+    g = np.random.default_rng(np.random.SeedSequence(seed).spawn(6)[5])
+    w = g.uniform(0.0, 1.0, size=(pat_rows, pat_cols, 4))
+    dark = g.integers(0, 4, size=(pat_rows, pat_cols))
+    np.put_along_axis(w, dark[..., None], g.uniform(0.0, 0.1, size=(pat_rows, pat_cols, 1)), axis=2)
+    return w
+
+
+def shape_weights(tile: np.ndarray, shape: int = THREE_QUARTER) -> np.ndarray:
+    """The 0/1 weight tile of a code tile under a pixel shape."""
+    q = np.arange(4)
+    return (((shape >> (q[None, None, :] ^ tile[..., None].astype(np.int64))) & 1)).astype(np.float64)
 
 
 # Workloads. ``pattern`` is the tile size in sensor pixels; None means the
