@@ -31,7 +31,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from synth import batch_cases, make_case  # noqa: E402
+from synth import batch_cases, make_case, random_weights, sense_weights, synthetic_image  # noqa: E402
 
 W, B, RHO, GAMMA = 32, 4, 0.7, 0.5
 FLOPS_PER_FREQ_ITER = 30          # factorised form: projection 18, metric 4, update 8
@@ -56,6 +56,9 @@ WORKLOADS = {
     "dense512": dict(kind="frame", rows=512, cols=512, period=4, iters=100, noise=0.0, path="fp64_dense",
                      desc="512x512 frame, recurrent 4x4-sensor pattern, FP64 dense form (per-class C of "
                           "eq. (14) in device memory)"),
+    "weights512": dict(kind="weights", rows=512, cols=512, period=4, iters=100, noise=0.0, path="fp64_dense",
+                       desc="512x512 frame, general layout (random per-pixel quadrant weights, recurrent "
+                            "4x4-sensor tile), FP64 dense form"),
 }
 HBM_PEAK_GBPS = 8000.0            # MI355X HBM3E
 DENSE_KERNEL_SOURCES = ["paper_2205_02646_amd/csrc/ljsde_dense.hip", "paper_2205_02646_amd/csrc/ljsde_window.h",
@@ -84,7 +87,7 @@ def load_traffic(workload: str, sources=None):
 
 
 def _oracle_worker(args):
-    y, tile, blocks, iters, shape = args
+    y, tile, blocks, iters, shape, weights = args
     from oracle import ljsde_oracle as O
     try:
         from threadpoolctl import threadpool_limits
@@ -92,11 +95,12 @@ def _oracle_worker(args):
     except Exception:  # pragma: no cover
         pass
     out = O.reconstruct(y, tile, W=W, B=B, iters=iters, rho=RHO, gamma=GAMMA, form="RL", blocks=blocks,
-                        shape=shape)
+                        shape=shape, weights=weights)
     return [(bi, bj, out[B * bi:B * bi + B, B * bj:B * bj + B]) for bi, bj in blocks]
 
 
-def cpu_baseline(y, tile, iters: int, n_windows: int, seed: int = 1, label: str = "", shape: int = 0xE):
+def cpu_baseline(y, tile, iters: int, n_windows: int, seed: int = 1, label: str = "", shape: int = 0xE,
+                 weights=None):
     """Time the FP64 oracle (RL-JSDE form) on a random sample of windows over
     the host cores; returns (record, {block: output})."""
     import multiprocessing as mp
@@ -109,7 +113,7 @@ def cpu_baseline(y, tile, iters: int, n_windows: int, seed: int = 1, label: str 
     chunks = [blocks[k::cores] for k in range(cores)]
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores) as pool:
-        parts = pool.map(_oracle_worker, [(y, tile, c, iters, shape) for c in chunks if c])
+        parts = pool.map(_oracle_worker, [(y, tile, c, iters, shape, weights) for c in chunks if c])
     dt = time.perf_counter() - t0
     res = {(bi, bj): blk for part in parts for bi, bj, blk in part}
     rec = {"value": n_windows * B * B / dt / 1e6, "unit": "MP/s", "cores": cores, "kind": "oracle",
@@ -120,6 +124,10 @@ def cpu_baseline(y, tile, iters: int, n_windows: int, seed: int = 1, label: str 
 
 
 def build_inputs(wl: dict):
+    if wl["kind"] == "weights":
+        wt = random_weights(wl["period"], wl["period"], seed=0)
+        clean, observed = synthetic_image(wl["rows"], wl["cols"], seed=0, noise_sigma=wl["noise"])
+        return [dict(clean=clean, tile=None, weights=wt, y=sense_weights(observed, wt))]
     if wl["kind"] == "frame":
         return [make_case(wl["rows"], wl["cols"], wl["period"], seed=0, noise=wl["noise"],
                           shape=wl.get("shape", 0xE))]
@@ -136,15 +144,21 @@ def run_dense(args, wl, cases):
     oracle_rec, oracle64_blocks = None, {}
     if not args.no_oracle:
         oracle_rec, oracle64_blocks = cpu_baseline(c["y"], c["tile"], iters, args.oracle_windows,
-                                                   label=wl["desc"].split(",")[0])
+                                                   label=wl["desc"].split(",")[0], weights=c.get("weights"))
     import torch
     from paper_2205_02646_amd import ljsde
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     y = torch.from_numpy(c["y"]).to(dev)
     rows, cols = 2 * y.shape[0], 2 * y.shape[1]
-    pd = ljsde.plan(c["tile"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA, fp64=True, dense_c=True)
-    pf = ljsde.plan(c["tile"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA, fp64=True)
+    general = c.get("weights") is not None
+    if general:  # general layouts run on the dense form only
+        pd = ljsde.plan_weights(c["weights"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA)
+        pf = None
+    else:
+        pd = ljsde.plan(c["tile"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA, fp64=True,
+                        dense_c=True)
+        pf = ljsde.plan(c["tile"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA, fp64=True)
     od = torch.empty((rows, cols), dtype=torch.float64, device=dev)
     of = torch.empty_like(od)
 
@@ -173,12 +187,16 @@ def run_dense(args, wl, cases):
 
     # the first call builds the dense C of the image size (not timed)
     msd = timed(lambda: ljsde.reconstruct(y, pd, out=od, stream=stream), args.steps, max(1, args.warmup))
-    msf = timed(lambda: ljsde.reconstruct(y, pf, out=of, stream=stream), max(2, min(args.steps // 4, 5)), 1)
+    msf = None
+    if pf is not None:
+        msf = timed(lambda: ljsde.reconstruct(y, pf, out=of, stream=stream), max(2, min(args.steps // 4, 5)), 1)
     ljsde.synchronize(stream)
     px = rows * cols
     nwin = (rows // B) * (cols // B)
     o = od.cpu().numpy()
-    quality = {"maxabs_dense_vs_factorised_fp64": float(torch.max(torch.abs(od - of)))}
+    quality = {}
+    if pf is not None:
+        quality["maxabs_dense_vs_factorised_fp64"] = float(torch.max(torch.abs(od - of)))
     if oracle64_blocks:
         quality["maxabs_dense_vs_oracle_sample"] = max(
             float(np.max(np.abs(o[B * i:B * i + B, B * j:B * j + B] - blk))) for (i, j), blk in oracle64_blocks.items())
@@ -203,8 +221,8 @@ def run_dense(args, wl, cases):
                                "(FP64 single-image launch)",
                    "name": args.workload, "images": 1, "megapixels": px / 1e6, "window": W, "block": B,
                    "iters": iters, "windows": nwin},
-        "fp64_plain": {"value": px / 1e6 / (msf * 1e-3), "unit": "MP/s", "ms_per_step": msf,
-                       "form": "factorised"},
+        "fp64_plain": None if msf is None else {"value": px / 1e6 / (msf * 1e-3), "unit": "MP/s",
+                                                "ms_per_step": msf, "form": "factorised"},
         "quality": quality,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,

@@ -61,13 +61,15 @@ enum {
     LJSDE_STATE_FP32 = 16,    /* FP32 plans: keep the loop state and its updates in FP32 too
                                  (no FP64 re-decision); greedy selections can then diverge
                                  from FP64 at near ties */
-    LJSDE_DENSE_C = 32        /* FP64 plans: the dense form of Sec. IV. Per class the full
+    LJSDE_DENSE_C = 32,       /* FP64 plans: the dense form of Sec. IV. Per class the full
                                  W^2 x W^2 matrix C of eq. (14) is built in device memory
                                  (16 MiB per class at W = 32, on the first reconstruction of an
                                  image size; LJSDE_ENOMEM if it does not fit), each window
                                  keeps R of eq. (12) for all W^2 frequencies and subtracts a
                                  column of C per iteration (eq. (17)). Same results as the
                                  factorised FP64 path; single-image calls only */
+    LJSDE_WEIGHTS = 64        /* reported by ljsde_plan_info for plans made by
+                                 ljsde_plan_weights (ignored there, refused by ljsde_plan) */
 };
 
 /*
@@ -111,6 +113,33 @@ enum {
 int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols,
                int window, int block, int iters, double rho, double gamma,
                unsigned flags);
+
+/*
+ * ljsde_plan_weights -- validate and register a plan for a general layout of
+ * the 2x2-footprint sensor (Sec. II, eq. (1): every measurement is a weighted
+ * sum of the high-resolution pixels under its sensor pixel; Sec. I: RL-JSDE
+ * applies to any recurrent layout). Sensor pixel (i, j) weighs quadrant
+ * q = 2*a + b of its footprint (row 2i + a, column 2j + b of the
+ * reconstruction) by weights[((i % pat_rows) * pat_cols + (j % pat_cols)) * 4 + q].
+ *  weights   host, pat_rows x pat_cols x 4 finite doubles (copied; the
+ *            caller keeps ownership). 0/1 weights of a pixel shape give that
+ *            shape's measurement matrix.
+ *  window, block, iters, rho, gamma  as for ljsde_plan.
+ *  flags     LJSDE_FP64 | LJSDE_DENSE_C, optionally LJSDE_Q_ONES; no pixel
+ *            shape. Other precisions or the factorised form ->
+ *            LJSDE_EUNSUPPORTED.
+ * Per class the tables hold the ten spectra S_qq' = DFT(w A_q A_q') (q <= q')
+ * and the per-pixel weights; C of eq. (14) is built from them on the device.
+ * A layout under which some frequency leaves no trace in a window (D = 0 in
+ * exact arithmetic, e.g. equal weights on all four quadrants at sigma = W/2)
+ * makes eq. (11) decide on rounding noise there; such layouts are accepted,
+ * but the selection at those frequencies is not reproducible across
+ * implementations.
+ * Returns a pattern id >= 0, or a negative status. Needs no GPU.
+ */
+int ljsde_plan_weights(const double *weights, int pat_rows, int pat_cols,
+                       int window, int block, int iters, double rho, double gamma,
+                       unsigned flags);
 
 /*
  * ljsde_set_energy_floor -- optional stopping test (Sec. IV: iterate up to
@@ -199,9 +228,13 @@ int ljsde_class_count(int pattern_id, int sensor_rows, int sensor_cols,
  *         S_o(k, l) = sum over the class's present sensor pixels (i', j') with
  *         code o of w(i', j') exp(-2 pi i (i' k + j' l) / Ws), Ws = W/2
  *         (the factorised form of C, eq. (14)); index [k*Ws + l][o][re, im].
+ *         Plans of ljsde_plan_weights: [Ws*Ws][10][2], the spectra of
+ *         w(i', j') A(i', j', q) A(i', j', q') for the pairs q <= q' in the
+ *         order (0,0) (0,1) (0,2) (0,3) (1,1) (1,2) (1,3) (2,2) (2,3) (3,3).
  *  D      host double [W*W] or NULL: the normaliser of eq. (13).
  *  codes  host int8 [Ws*Ws] or NULL: pattern code per local sensor pixel,
- *         -1 where the pixel lies outside the image.
+ *         -1 where the pixel lies outside the image (0 inside for plans of
+ *         ljsde_plan_weights).
  */
 int ljsde_class_tables(int pattern_id, int sensor_rows, int sensor_cols, int class_index,
                        double *S, double *D, int8_t *codes);

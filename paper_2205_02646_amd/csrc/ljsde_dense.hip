@@ -67,6 +67,63 @@ __global__ __launch_bounds__(256) void dense_c_build_kernel(KParams p, const uns
     }
 }
 
+// Index of the spectrum S_qq' (q <= q') in the general-layout class tables:
+// (0,0) (0,1) (0,2) (0,3) (1,1) (1,2) (1,3) (2,2) (2,3) (3,3).
+__device__ __forceinline__ int pair_index(int q, int r) {
+    const int a = q < r ? q : r, b = q < r ? r : q;
+    return 4 * a - (a * (a - 1)) / 2 + (b - a);
+}
+
+// Column g of C for a general layout (per-pixel quadrant weights A_m(q)):
+// with a_m(f) = exp(i theta 2 (i' sigma + j' rho)) sum_q A_m(q) e_q(f) and
+// e_q(f) = exp(i theta (qa sigma + qb rho)),
+//     C(f, g) = sum_{q, q'} conj(e_q(f)) e_q'(g) S_qq'(f - g),
+// S_qq'(k, l) = sum_m w_m A_m(q) A_m(q') exp(-2 pi i (i' k + j' l) / Ws).
+// Same output order and grid as dense_c_build_kernel.
+template <int WS>
+__global__ __launch_bounds__(256) void dense_c_build_general_kernel(KParams p, const unsigned char *tables,
+                                                                    double2 *out) {
+    constexpr int W = 2 * WS, NF = W * W;
+    const int g = blockIdx.x;
+    const int cls = blockIdx.y;
+    const double *S = (const double *)(tables + (size_t)cls * p.lay.stride + p.lay.offS);
+    const double *ew = p.c.ew;
+    const int sg = g / W, rg = g % W;
+    const int kg = sg & (WS - 1), lg = rg & (WS - 1);
+    double egr[4], egi[4];  // e_q'(g)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int ph = ((q >> 1) * sg + (q & 1) * rg) & (W - 1);
+        egr[q] = ew[2 * ph];
+        egi[q] = ew[2 * ph + 1];
+    }
+    double2 *col = out + ((size_t)cls * NF + g) * NF;
+    for (int e = threadIdx.x; e < NF; e += blockDim.x) {
+        const int L = e & 63, tc = e >> 6;
+        const int f = dense_freq<WS>(L, tc >> 2, tc & 3);
+        const int sf = f / W, rf = f % W;
+        const int pos = ((sf - kg) & (WS - 1)) * WS + ((rf - lg) & (WS - 1));
+        const double *Sp = S + (size_t)pos * 20;
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double tr = 0.0, ti = 0.0;  // sum_q' e_q'(g) S_qq'
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k = pair_index(q, r);
+                const double sr = Sp[2 * k], si = Sp[2 * k + 1];
+                tr += egr[r] * sr - egi[r] * si;
+                ti += egr[r] * si + egi[r] * sr;
+            }
+            const int ph = ((q >> 1) * sf + (q & 1) * rf) & (W - 1);
+            const double cr = ew[2 * ph], ci = -ew[2 * ph + 1];  // conj(e_q(f))
+            re += cr * tr - ci * ti;
+            im += cr * ti + ci * tr;
+        }
+        col[e] = make_double2(re, im);
+    }
+}
+
 // LDS of one wavefront: w*y [NPOS] FP64, codes [NPOS], and the VALU DFT's
 // stage [NPOS][4] complex for WS = 8 only
 template <int WS>
@@ -76,7 +133,8 @@ struct DenseLds {
     static constexpr size_t bytes = stage + (size_t)NPOS * 8 + NPOS;
 };
 
-// One wavefront per window.
+// One wavefront per window. SHAPE is a pixel-shape mask or SHAPE_GENERAL
+// (per-pixel quadrant weights: P_q of every quadrant, R = sum_q conj(e_q) P_q).
 template <int WS, int SHAPE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void dense_kernel(
     KParams p, KJob j, const double2 *__restrict__ Cd) {
@@ -100,7 +158,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void de
     double *ldsX = (double *)(lds + LL::stage);
     signed char *ldsC = (signed char *)(lds + LL::stage + (size_t)NPOS * 8);
     C2<double> P[QPL][4];
-    const double e0 = window_prologue<double, WS>(p, j, bi, bj, codes, ldsX, ldsC, ldsS, P);
+    constexpr bool GENERAL = SHAPE == SHAPE_GENERAL;
+    constexpr int PSHAPE = GENERAL ? SHAPE_QUARTER : SHAPE;  // Q_q = P_q
+    const double *Aw = GENERAL ? (const double *)(tb + p.lay.offA) : nullptr;
+    const double e0 = window_prologue<double, WS, GENERAL>(p, j, bi, bj, codes, ldsX, ldsC, ldsS, P, Aw);
 
     // R(0) of eq. (12) through the factorised projection, and q / D
     const double *ew = p.c.ew;
@@ -112,7 +173,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void de
         const int kap = krow + KSTEP * t;
         const C2<double> tk = {ew[2 * kap], -ew[2 * kap + 1]};
         const C2<double> tkl = {ew[2 * (kap + lam)], -ew[2 * (kap + lam) + 1]};
-        project4<double, SHAPE>(P[t], tl, tk, tkl, R[t]);
+        project4<double, PSHAPE>(P[t], tl, tk, tkl, R[t]);
 #pragma unroll
         for (int c = 0; c < 4; ++c) qd[t][c] = qD64[dense_freq<WS>(lane, t, c)];
     }
@@ -210,10 +271,14 @@ int launch_dense_c_build(const KParams &p, const unsigned char *tables, int n_cl
     if (n_classes <= 0) return 0;
     const int nf = (2 * ws) * (2 * ws);
     const dim3 grid((unsigned)nf, (unsigned)n_classes);
-    if (ws == 16)
-        dense_c_build_kernel<16><<<grid, dim3(256), 0, (hipStream_t)stream>>>(p, tables, (double2 *)out);
-    else
-        dense_c_build_kernel<8><<<grid, dim3(256), 0, (hipStream_t)stream>>>(p, tables, (double2 *)out);
+    hipStream_t st = (hipStream_t)stream;
+    if (p.shape == SHAPE_GENERAL) {
+        if (ws == 16) dense_c_build_general_kernel<16><<<grid, dim3(256), 0, st>>>(p, tables, (double2 *)out);
+        else dense_c_build_general_kernel<8><<<grid, dim3(256), 0, st>>>(p, tables, (double2 *)out);
+    } else {
+        if (ws == 16) dense_c_build_kernel<16><<<grid, dim3(256), 0, st>>>(p, tables, (double2 *)out);
+        else dense_c_build_kernel<8><<<grid, dim3(256), 0, st>>>(p, tables, (double2 *)out);
+    }
     return (int)hipGetLastError();
 }
 
@@ -227,7 +292,9 @@ static int launch_dense_t(const KParams &p, const KJob &job, const void *C, void
 }
 
 int launch_dense(const KParams &p, const KJob &job, const void *C, int ws, void *stream) {
-    constexpr int TQ = SHAPE_THREE_QUARTER, QS = SHAPE_QUARTER;
+    constexpr int TQ = SHAPE_THREE_QUARTER, QS = SHAPE_QUARTER, GN = SHAPE_GENERAL;
+    if (p.shape == GN)
+        return ws == 16 ? launch_dense_t<16, GN>(p, job, C, stream) : launch_dense_t<8, GN>(p, job, C, stream);
     if (p.shape == QS)
         return ws == 16 ? launch_dense_t<16, QS>(p, job, C, stream) : launch_dense_t<8, QS>(p, job, C, stream);
     return ws == 16 ? launch_dense_t<16, TQ>(p, job, C, stream) : launch_dense_t<8, TQ>(p, job, C, stream);

@@ -138,19 +138,28 @@ typedef double v4f64 __attribute__((ext_vector_type(4)));
 // with P_o(L / 16 + 4t, L % 16) in register t: the positions this lane owns.
 // X is w * y in LDS ([i][j], absent pixels 0), Cd the codes, dft the table of
 // e^{-2 pi i k / 16}. Needs the whole wavefront active.
-template <typename XT>
+// WEIGHTED: general per-pixel quadrant weights instead of codes,
+//     P_q(k, l) = sum_{i, j} X(i, j) A(i, j, q) e^{-2 pi i (i k + j l) / 16}
+// with Aw = A as [i * 16 + j][q] (Cd unused).
+template <typename XT, bool WEIGHTED = false>
 __device__ __forceinline__ void dft16_mfma(const XT *X, const signed char *Cd, const double *dft,
-                                           double Pre[4][4], double Pim[4][4]) {
+                                           double Pre[4][4], double Pim[4][4], const double *Aw = nullptr) {
     int lane = threadIdx.x & 63;
     asm volatile("" : "+v"(lane));  // per call: lane-derived addresses are not hoisted into registers
     const int r16 = lane & 15, q = lane >> 4;
     double x[4], gr[4], gi[4];
     int cd[4];
+    double aw[4][4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const int j = 4 * c + q;
         x[c] = (double)X[r16 * 16 + j];
-        cd[c] = Cd[r16 * 16 + j];
+        if constexpr (WEIGHTED) {
+#pragma unroll
+            for (int o = 0; o < 4; ++o) aw[c][o] = Aw[(r16 * 16 + j) * 4 + o];
+        } else {
+            cd[c] = Cd[r16 * 16 + j];
+        }
         const int k = (j * r16) & 15;
         gr[c] = dft[2 * k];
         gi[c] = dft[2 * k + 1];
@@ -160,7 +169,9 @@ __device__ __forceinline__ void dft16_mfma(const XT *X, const signed char *Cd, c
         v4f64 tr = {0.0, 0.0, 0.0, 0.0}, ti = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const double a = cd[c] == o ? x[c] : 0.0;
+            double a;
+            if constexpr (WEIGHTED) a = x[c] * aw[c][o];
+            else a = cd[c] == o ? x[c] : 0.0;
             tr = __builtin_amdgcn_mfma_f64_16x16x4f64(a, gr[c], tr, 0, 0, 0);
             ti = __builtin_amdgcn_mfma_f64_16x16x4f64(a, gi[c], ti, 0, 0, 0);
         }

@@ -96,24 +96,27 @@ struct Plan {
     int pr = 0, pc = 0, W = 0, B = 0, Ws = 0, iters = 0;
     double rho = 0, gamma = 0, tau = 0;
     unsigned flags = 0;
-    int shape = 0xE;                    // pixel-shape mask of quadrant offsets
+    int shape = 0xE;                    // pixel-shape mask of quadrant offsets, or SHAPE_GENERAL
+    std::vector<double> quad;           // general layouts: [pr][pc][4] quadrant weights per pixel
     ClassLayout lay{};
     std::vector<double> w, ew, dft, q, H;  // class-independent FP64 tables
     int device = -1;
     double *d_consts = nullptr;         // w | ew | dft | H
     std::map<std::pair<int, int>, std::unique_ptr<SizeSet>> sizes;
     bool fp64() const { return (flags & LJSDE_FP64) != 0; }
+    bool general() const { return shape == SHAPE_GENERAL; }
+    int n_spectra() const { return general() ? 10 : 4; }
 };
 
 std::mutex g_mu;
 std::vector<std::unique_ptr<Plan>> g_plans;
 
-ClassLayout make_layout(int W, int Ws) {
+ClassLayout make_layout(int W, int Ws, bool general) {
     ClassLayout L{};
     auto al = [](int x) { return (x + 255) & ~255; };
     int off = 0;
     L.offS = off;
-    off = al(off + Ws * Ws * 4 * 2 * (int)sizeof(double));
+    off = al(off + Ws * Ws * (general ? 10 : 4) * 2 * (int)sizeof(double));
     L.offQD64 = off;
     off = al(off + W * W * (int)sizeof(double));
     L.offInvD = off;
@@ -122,6 +125,11 @@ ClassLayout make_layout(int W, int Ws) {
     off = al(off + W * W * (int)sizeof(float));
     L.offCodes = off;
     off = al(off + Ws * Ws);
+    L.offA = -1;
+    if (general) {
+        L.offA = off;
+        off = al(off + Ws * Ws * 4 * (int)sizeof(double));
+    }
     L.stride = off;
     return L;
 }
@@ -217,12 +225,101 @@ void enumerate(const Plan &p, SizeSet &s) {
     }
 }
 
+// q / D, 1 / D (0 where D <= 0) of one class
+void store_normaliser(const Plan &p, const double *D, unsigned char *dst) {
+    double *qd = (double *)(dst + p.lay.offQD64);
+    double *inv = (double *)(dst + p.lay.offInvD);
+    float *qd32 = (float *)(dst + p.lay.offQD32);
+    for (int f = 0; f < p.W * p.W; ++f) {
+        const bool pos = D[f] > 0;
+        qd[f] = pos ? p.q[f] / D[f] : 0.0;
+        inv[f] = pos ? 1.0 / D[f] : 0.0;
+        qd32[f] = (float)qd[f];
+    }
+}
+
+// 2-D Ws-point DFT of a real tile v [Ws][Ws]:
+// out[(k * Ws + l) * ostride + {0, 1}] = sum_{i, j} v(i, j) e^{-2 pi i (i k + j l) / Ws}, row pass first.
+void dft2_real(const Plan &p, const double *v, double *out, int ostride) {
+    const int Ws = p.Ws;
+    std::vector<double> A((size_t)Ws * Ws * 2, 0.0);  // [i][l][re, im]
+    for (int i = 0; i < Ws; ++i)
+        for (int l = 0; l < Ws; ++l) {
+            double re = 0, im = 0;
+            for (int j = 0; j < Ws; ++j) {
+                const int t = (j * l) % Ws;
+                re += v[i * Ws + j] * p.dft[2 * t];
+                im += v[i * Ws + j] * p.dft[2 * t + 1];
+            }
+            A[(i * Ws + l) * 2] = re;
+            A[(i * Ws + l) * 2 + 1] = im;
+        }
+    for (int k = 0; k < Ws; ++k)
+        for (int l = 0; l < Ws; ++l) {
+            double re = 0, im = 0;
+            for (int i = 0; i < Ws; ++i) {
+                const int t = (i * k) % Ws;
+                const double ar = A[(i * Ws + l) * 2], ai = A[(i * Ws + l) * 2 + 1];
+                re += ar * p.dft[2 * t] - ai * p.dft[2 * t + 1];
+                im += ar * p.dft[2 * t + 1] + ai * p.dft[2 * t];
+            }
+            out[(size_t)(k * Ws + l) * ostride] = re;
+            out[(size_t)(k * Ws + l) * ostride + 1] = im;
+        }
+}
+
+// Per-class FP64 tables of a general layout (Sec. II, eq. (1): pixel m weighs
+// quadrant q = 2a + b of its footprint by A_m(q)). With
+// a_m(f) = exp(i theta 2 (i' sigma + j' rho)) sum_q A_m(q) e_q(f) and
+// e_q(f) = exp(i theta (a sigma + b rho)), C of eq. (14) is
+// sum_{q, q'} conj(e_q(f)) e_q'(g) S_qq'(f - g) with the ten spectra
+// S_qq' = DFT(w A_q A_q') (q <= q'), and D of eq. (13) is C(f, f).
+void build_class_general(const Plan &p, const AxisKey &rk, const AxisKey &ck, unsigned char *dst, double *Dout) {
+    const int W = p.W, Ws = p.Ws;
+    std::vector<double> A((size_t)Ws * Ws * 4, 0.0);
+    signed char *cd = (signed char *)(dst + p.lay.offCodes);
+    for (int i = 0; i < Ws; ++i)
+        for (int j = 0; j < Ws; ++j) {
+            const bool valid = i >= rk.lo && i < Ws - rk.hi && j >= ck.lo && j < Ws - ck.hi;
+            cd[i * Ws + j] = valid ? 0 : -1;
+            if (!valid) continue;
+            const double *src = &p.quad[((size_t)pmod(rk.phase + i, p.pr) * p.pc + pmod(ck.phase + j, p.pc)) * 4];
+            for (int q = 0; q < 4; ++q) A[(i * Ws + j) * 4 + q] = src[q];
+        }
+    memcpy(dst + p.lay.offA, A.data(), A.size() * sizeof(double));
+    double *S = (double *)(dst + p.lay.offS);
+    std::vector<double> v((size_t)Ws * Ws);
+    double mass[4][4];
+    int idx = 0;
+    for (int q = 0; q < 4; ++q)
+        for (int r = q; r < 4; ++r, ++idx) {
+            for (int m = 0; m < Ws * Ws; ++m) v[m] = p.w[m] * A[m * 4 + q] * A[m * 4 + r];
+            dft2_real(p, v.data(), S + 2 * idx, 20);
+            mass[q][r] = mass[r][q] = S[2 * idx];  // S_qq'(0, 0)
+        }
+    for (int sg = 0; sg < W; ++sg)
+        for (int rh = 0; rh < W; ++rh) {
+            double D = 0;
+            for (int q = 0; q < 4; ++q)
+                for (int r = 0; r < 4; ++r) {
+                    const int ph = pmod(((r >> 1) - (q >> 1)) * sg + ((r & 1) - (q & 1)) * rh, W);
+                    D += mass[q][r] * p.ew[2 * ph];  // Re conj(e_q) e_r
+                }
+            Dout[sg * W + rh] = D;
+        }
+    store_normaliser(p, Dout, dst);
+}
+
 // Per-class FP64 tables. With a_m(sigma, rho) = exp(i theta (2i' sigma + 2j' rho)) H_o(sigma, rho)
 // the diagonal of C (eq. (13)) is D = sum_o |H_o|^2 S_o(0, 0).
 void build_class(const Plan &p, const SizeSet &s, int cls, unsigned char *dst, double *Dout) {
     const int W = p.W, Ws = p.Ws;
     const AxisKey &rk = s.rowkeys[cls / (int)s.colkeys.size()];
     const AxisKey &ck = s.colkeys[cls % (int)s.colkeys.size()];
+    if (p.general()) {
+        build_class_general(p, rk, ck, dst, Dout);
+        return;
+    }
     std::vector<int> code(Ws * Ws);
     for (int i = 0; i < Ws; ++i)
         for (int j = 0; j < Ws; ++j) {
@@ -762,14 +859,16 @@ int ljsde_plan_info(int pattern_id, int *window, int *block, int *iters, unsigne
 
 const char *ljsde_last_error(void) { return g_last_error.c_str(); }
 
-int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, int block, int iters,
-               double rho, double gamma, unsigned flags) {
-    if (!pattern) return fail(LJSDE_EINVAL, "pattern is null");
+}  // extern "C"
+
+namespace {
+
+// Checks shared by both plan constructors: pattern size, window geometry,
+// iteration count, rho and gamma.
+int check_plan_args(int pat_rows, int pat_cols, int window, int block, int iters, double rho, double gamma) {
     if (pat_rows <= 0 || pat_cols <= 0)
         return fail(LJSDE_EINVAL, "pattern size %dx%d must be positive", pat_rows, pat_cols);
     if ((long long)pat_rows * pat_cols > (1LL << 28)) return fail(LJSDE_EINVAL, "pattern too large");
-    for (long long i = 0; i < (long long)pat_rows * pat_cols; ++i)
-        if (pattern[i] > 3) return fail(LJSDE_EINVAL, "pattern code %d at %lld not in 0..3", pattern[i], i);
     if (window <= 0 || block <= 0 || window % 2 || block % 2 || block > window || (window - block) % 4)
         return fail(LJSDE_EINVAL,
                     "window %d / block %d: need even sizes, block <= window, (window - block) %% 4 == 0",
@@ -777,6 +876,30 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, i
     if (iters < 1) return fail(LJSDE_EINVAL, "iters %d must be >= 1", iters);
     if (!(rho > 0.0 && rho <= 1.0)) return fail(LJSDE_EINVAL, "rho %g must be in (0, 1]", rho);
     if (!(gamma > 0.0 && gamma < 2.0)) return fail(LJSDE_EINVAL, "gamma %g must be in (0, 2)", gamma);
+    return LJSDE_OK;
+}
+
+int register_plan(std::unique_ptr<Plan> p) {
+    p->Ws = p->W / 2;
+    p->lay = make_layout(p->W, p->Ws, p->general());
+    build_constants(*p);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_plans.push_back(std::move(p));
+    ok();
+    return (int)g_plans.size() - 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, int block, int iters,
+               double rho, double gamma, unsigned flags) {
+    if (!pattern) return fail(LJSDE_EINVAL, "pattern is null");
+    int st = check_plan_args(pat_rows, pat_cols, window, block, iters, rho, gamma);
+    if (st) return st;
+    for (long long i = 0; i < (long long)pat_rows * pat_cols; ++i)
+        if (pattern[i] > 3) return fail(LJSDE_EINVAL, "pattern code %d at %lld not in 0..3", pattern[i], i);
     const unsigned known = LJSDE_FP64 | LJSDE_FP32 | LJSDE_DFT_SPLITBF16 | LJSDE_Q_ONES | LJSDE_STATE_FP32 |
                            LJSDE_DENSE_C | LJSDE_SHAPE(15);
     if (flags & ~known) return fail(LJSDE_EINVAL, "unknown flags 0x%x", flags & ~known);
@@ -806,18 +929,52 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, i
     p->pc = pat_cols;
     p->W = window;
     p->B = block;
-    p->Ws = window / 2;
     p->iters = iters;
     p->rho = rho;
     p->gamma = gamma;
     p->flags = flags;
     p->shape = shape;
-    p->lay = make_layout(p->W, p->Ws);
-    build_constants(*p);
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_plans.push_back(std::move(p));
-    ok();
-    return (int)g_plans.size() - 1;
+    return register_plan(std::move(p));
+}
+
+int ljsde_plan_weights(const double *weights, int pat_rows, int pat_cols, int window, int block, int iters,
+                       double rho, double gamma, unsigned flags) {
+    if (!weights) return fail(LJSDE_EINVAL, "weights is null");
+    int st = check_plan_args(pat_rows, pat_cols, window, block, iters, rho, gamma);
+    if (st) return st;
+    const long long n = (long long)pat_rows * pat_cols * 4;
+    for (long long i = 0; i < n; ++i)
+        if (!std::isfinite(weights[i])) return fail(LJSDE_EINVAL, "weight %lld is not finite", i);
+    const unsigned known = LJSDE_FP64 | LJSDE_FP32 | LJSDE_DFT_SPLITBF16 | LJSDE_Q_ONES | LJSDE_STATE_FP32 |
+                           LJSDE_DENSE_C | LJSDE_SHAPE(15) | LJSDE_WEIGHTS;
+    if (flags & ~known) return fail(LJSDE_EINVAL, "unknown flags 0x%x", flags & ~known);
+    if (flags & LJSDE_SHAPE(15)) return fail(LJSDE_EINVAL, "a pixel shape does not apply to a weights plan");
+    if (((flags & LJSDE_FP64) != 0) == ((flags & LJSDE_FP32) != 0))
+        return fail(LJSDE_EINVAL, "exactly one of LJSDE_FP64 / LJSDE_FP32 is required");
+    if ((flags & (LJSDE_DFT_SPLITBF16 | LJSDE_STATE_FP32)) && (flags & LJSDE_FP64))
+        return fail(LJSDE_EINVAL, "LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32 apply to FP32 plans only");
+    if ((flags & LJSDE_DENSE_C) && !(flags & LJSDE_FP64))
+        return fail(LJSDE_EINVAL, "LJSDE_DENSE_C applies to FP64 plans only");
+    if (!(window == 32 || window == 16))
+        return fail(LJSDE_EUNSUPPORTED, "no kernel for window %d (have 16, 32)", window);
+    if (!(block == 4 || block == 8))
+        return fail(LJSDE_EUNSUPPORTED, "no kernel for block %d (have 4, 8)", block);
+    if (iters > 32767) return fail(LJSDE_EUNSUPPORTED, "iters %d above 32767", iters);
+    if ((flags & (LJSDE_FP64 | LJSDE_DENSE_C)) != (LJSDE_FP64 | LJSDE_DENSE_C))
+        return fail(LJSDE_EUNSUPPORTED, "general layouts run on the dense FP64 form only (LJSDE_FP64 | LJSDE_DENSE_C)");
+    auto p = std::make_unique<Plan>();
+    p->quad.assign(weights, weights + n);
+    p->pattern.assign((size_t)pat_rows * pat_cols, 0);
+    p->pr = pat_rows;
+    p->pc = pat_cols;
+    p->W = window;
+    p->B = block;
+    p->iters = iters;
+    p->rho = rho;
+    p->gamma = gamma;
+    p->flags = flags | LJSDE_WEIGHTS;
+    p->shape = SHAPE_GENERAL;
+    return register_plan(std::move(p));
 }
 
 int ljsde_set_energy_floor(int pattern_id, double tau) {
@@ -1021,7 +1178,7 @@ int ljsde_class_tables(int pattern_id, int sensor_rows, int sensor_cols, int cla
         return fail(LJSDE_EINVAL, "class %d out of range [0, %d)", class_index, s->n_classes());
     build_host_tables(*p, *s);
     const unsigned char *blk = s->blob.data() + (size_t)class_index * p->lay.stride;
-    if (S) memcpy(S, blk + p->lay.offS, sizeof(double) * p->Ws * p->Ws * 8);
+    if (S) memcpy(S, blk + p->lay.offS, sizeof(double) * p->Ws * p->Ws * 2 * p->n_spectra());
     if (D) memcpy(D, s->D.data() + (size_t)class_index * p->W * p->W, sizeof(double) * p->W * p->W);
     if (codes) memcpy(codes, blk + p->lay.offCodes, p->Ws * p->Ws);
     return ok();

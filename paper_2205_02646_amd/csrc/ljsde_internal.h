@@ -15,13 +15,20 @@ struct DevConsts {
                         // (its shape's quadrants) to the basis function (sigma, rho)
 };
 
+// KParams::shape of a plan with general per-pixel quadrant weights (Sec. II,
+// eq. (1): any 2x2-footprint layout), outside the range of the 4-bit masks.
+constexpr int SHAPE_GENERAL = 0x10;
+
 // Byte offsets inside one class block of the device table.
 struct ClassLayout {
-    int offS;      // double [Ws*Ws][4][2]  S_o(k, l)
+    int offS;      // double [Ws*Ws][4][2]  S_o(k, l); general layouts: [Ws*Ws][10][2]
+                   //                        S_qq'(k, l) for q <= q'
     int offQD64;   // double [W*W]          q / D   (0 where D <= 0)
     int offInvD;   // double [W*W]          1 / D   (0 where D <= 0)
     int offQD32;   // float  [W*W]          q / D
-    int offCodes;  // int8   [Ws*Ws]        code, -1 outside the image
+    int offCodes;  // int8   [Ws*Ws]        code, -1 outside the image (general layouts: 0)
+    int offA;      // double [Ws*Ws][4]     quadrant weights per pixel (general layouts
+                   //                        only, 0 outside the image), else -1
     int stride;    // bytes per class (multiple of 256)
 };
 
@@ -34,8 +41,8 @@ struct KParams {
     double ecoef;  // 2 gamma - gamma^2
     double tau;    // energy floor (0 = off)
     int dft_bf16;  // window DFT with split-BF16 MFMA products (FP32 plans)
-    int shape;     // pixel-shape mask (0xE three-quarter, 0x1 quarter): picks
-                   // the kernel instantiation on the host
+    int shape;     // pixel-shape mask (0xE three-quarter, 0x1 quarter) or
+                   // SHAPE_GENERAL: picks the kernel instantiation on the host
     DevConsts c;
     ClassLayout lay;
 };

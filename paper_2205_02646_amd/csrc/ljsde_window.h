@@ -21,10 +21,12 @@ struct WinLds {
 // positions x 4 orientations). `codes` are the class's per-pixel codes (-1
 // outside the image). LDS of the wavefront: ldsX [NPOS] (w*y), ldsC [NPOS]
 // (codes) and, for WS = 8 only (the VALU DFT), ldsS [NPOS * 8] (stage).
-template <typename T, int WS>
+// WEIGHTED (general layouts): P holds P_q = DFT(w * y * A_q) for the class's
+// per-pixel quadrant weights Aw [NPOS][4] instead of the code-masked spectra.
+template <typename T, int WS, bool WEIGHTED = false>
 __device__ __forceinline__ double window_prologue(const KParams &p, const KJob &j, int bi, int bj,
                                                   const signed char *codes, T *ldsX, signed char *ldsC, T *ldsS,
-                                                  C2<T> P[][4]) {
+                                                  C2<T> P[][4], const double *Aw = nullptr) {
     constexpr int QPL = WS * WS / 64;
     constexpr int NPOS = WS * WS;
     constexpr int KSTEP = 64 / WS;
@@ -60,7 +62,7 @@ __device__ __forceinline__ double window_prologue(const KParams &p, const KJob &
     // ---- orientation-masked weighted DFT -----------------------------------
     if constexpr (WS == 16) {
         double Pre[4][4], Pim[4][4];
-        dft16_mfma<T>(ldsX, ldsC, p.c.dft, Pre, Pim);
+        dft16_mfma<T, WEIGHTED>(ldsX, ldsC, p.c.dft, Pre, Pim, Aw);
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -81,7 +83,9 @@ __device__ __forceinline__ double window_prologue(const KParams &p, const KJob &
                 const T twr = (T)p.c.dft[2 * k], twi = (T)p.c.dft[2 * k + 1];
 #pragma unroll
                 for (int o = 0; o < 4; ++o) {
-                    const T xo = (c == o) ? x : T(0);
+                    T xo;
+                    if constexpr (WEIGHTED) xo = x * (T)Aw[(ip * WS + jp) * 4 + o];
+                    else xo = (c == o) ? x : T(0);
                     acc[o].re += xo * twr;
                     acc[o].im += xo * twi;
                 }

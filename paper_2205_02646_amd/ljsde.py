@@ -35,6 +35,7 @@ def SHAPE(mask: int) -> int:
     return (mask & 15) << 8
 STATE_FP32 = 16
 DENSE_C = 32
+WEIGHTS = 64  # reported by plan_info for plans of plan_weights
 
 _NAMES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOMEM: "ENOMEM", EHIP: "EHIP", EBADID: "EBADID"}
 
@@ -68,6 +69,7 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     i, d, u, vp = ctypes.c_int, ctypes.c_double, ctypes.c_uint, ctypes.c_void_p
     L.ljsde_plan.argtypes = [ctypes.POINTER(ctypes.c_uint8), i, i, i, i, i, d, d, u]
+    L.ljsde_plan_weights.argtypes = [ctypes.POINTER(ctypes.c_double), i, i, i, i, i, d, d, u]
     L.ljsde_set_energy_floor.argtypes = [i, d]
     L.ljsde_reconstruct.argtypes = [vp, i, i, i, vp, vp]
     L.ljsde_reconstruct_diag.argtypes = [vp, i, i, i, vp, vp, vp]
@@ -79,7 +81,7 @@ def lib():
     L.ljsde_class_count.argtypes = [i, i, i, vp]
     L.ljsde_class_tables.argtypes = [i, i, i, i, vp, vp, vp]
     L.ljsde_plan_info.argtypes = [i, vp, vp, vp, vp]
-    for name in ("ljsde_plan", "ljsde_set_energy_floor", "ljsde_reconstruct", "ljsde_reconstruct_diag",
+    for name in ("ljsde_plan", "ljsde_plan_weights", "ljsde_set_energy_floor", "ljsde_reconstruct", "ljsde_reconstruct_diag",
                  "ljsde_reconstruct_batch", "ljsde_autotune", "ljsde_synchronize", "ljsde_release",
                  "ljsde_class_count", "ljsde_class_tables", "ljsde_plan_info", "ljsde_version"):
         getattr(L, name).restype = ctypes.c_int
@@ -116,6 +118,19 @@ def plan(pattern, window: int = 32, block: int = 4, iters: int = 100, rho: float
              | (STATE_FP32 if state_fp32 else 0) | (DENSE_C if dense_c else 0) | SHAPE(shape))
     return _check(lib().ljsde_plan(pat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), pat.shape[0],
                                    pat.shape[1], window, block, iters, rho, gamma, flags))
+
+
+def plan_weights(weights, window: int = 32, block: int = 4, iters: int = 100, rho: float = 0.7,
+                 gamma: float = 0.5, q_ones: bool = False) -> int:
+    """Register a plan for a general layout: ``weights`` is a [rows, cols, 4]
+    tile of per-pixel quadrant weights (quadrant 2a + b of the footprint).
+    Runs on the dense FP64 form."""
+    wt = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+    if wt.ndim != 3 or wt.shape[2] != 4:
+        raise ValueError("weights must be a [rows, cols, 4] tile")
+    flags = FP64 | DENSE_C | (Q_ONES if q_ones else 0)
+    return _check(lib().ljsde_plan_weights(wt.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), wt.shape[0],
+                                           wt.shape[1], window, block, iters, rho, gamma, flags))
 
 
 def set_energy_floor(pid: int, tau: float) -> None:
@@ -220,9 +235,11 @@ def class_map(pid: int, sensor_rows: int, sensor_cols: int):
 
 
 def class_tables(pid: int, sensor_rows: int, sensor_cols: int, cls: int, window: int):
-    """FP64 tables of one class: (S [Ws*Ws, 4] complex, D [W*W], codes [Ws, Ws])."""
+    """FP64 tables of one class: (S [Ws*Ws, 4] complex, D [W*W], codes [Ws, Ws]);
+    S is [Ws*Ws, 10] (pairs q <= q') for plans of ``plan_weights``."""
     ws = window // 2
-    S = np.empty((ws * ws, 4, 2), dtype=np.float64)
+    nspec = 10 if plan_info(pid)["flags"] & WEIGHTS else 4
+    S = np.empty((ws * ws, nspec, 2), dtype=np.float64)
     D = np.empty(window * window, dtype=np.float64)
     codes = np.empty(ws * ws, dtype=np.int8)
     _check(lib().ljsde_class_tables(pid, sensor_rows, sensor_cols, cls, S.ctypes.data, D.ctypes.data,

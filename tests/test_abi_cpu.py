@@ -11,7 +11,7 @@ import pytest
 
 from oracle import ljsde_oracle as O
 from paper_2205_02646_amd import ljsde
-from synth import make_case, random_pattern
+from synth import make_case, random_pattern, random_weights
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -260,3 +260,92 @@ def test_batch_rejects_plans_that_need_another_kernel(other):
     assert st == ljsde.EINVAL and "job 1" in ljsde.last_error()
     ljsde.release(p0)
     ljsde.release(p1)
+
+
+WTILE = random_weights(3, 4, seed=5)
+
+
+@pytest.mark.parametrize("kwargs,flags,code", [
+    (dict(window=30), None, ljsde.EINVAL),
+    (dict(iters=0), None, ljsde.EINVAL),
+    (dict(gamma=2.0), None, ljsde.EINVAL),
+    (dict(window=64), None, ljsde.EUNSUPPORTED),
+    (dict(), ljsde.FP32, ljsde.EUNSUPPORTED),                       # dense FP64 form only
+    (dict(), ljsde.FP64, ljsde.EUNSUPPORTED),                       # not the factorised form
+    (dict(), ljsde.FP64 | ljsde.DENSE_C | ljsde.SHAPE(0x1), ljsde.EINVAL),  # no pixel shape
+    (dict(), ljsde.FP64 | ljsde.FP32 | ljsde.DENSE_C, ljsde.EINVAL),
+    (dict(), ljsde.FP64 | ljsde.DENSE_C | 0x10000, ljsde.EINVAL),
+])
+def test_plan_weights_validation(kwargs, flags, code):
+    args = dict(window=32, block=4, iters=10, rho=0.7, gamma=0.5)
+    args.update(kwargs)
+    wt = np.ascontiguousarray(WTILE)
+    f = (ljsde.FP64 | ljsde.DENSE_C) if flags is None else flags
+    st = ljsde.lib().ljsde_plan_weights(wt.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 3, 4,
+                                        args["window"], args["block"], args["iters"], args["rho"],
+                                        args["gamma"], f)
+    assert st == code and ljsde.last_error()
+
+
+def test_plan_weights_rejects_non_finite_weights_and_null():
+    wt = WTILE.copy()
+    wt[1, 2, 3] = np.nan
+    with pytest.raises(ljsde.LjsdeError) as e:
+        ljsde.plan_weights(wt)
+    assert e.value.code == ljsde.EINVAL and "not finite" in ljsde.last_error()
+    st = ljsde.lib().ljsde_plan_weights(None, 3, 4, 32, 4, 10, 0.7, 0.5, ljsde.FP64 | ljsde.DENSE_C)
+    assert st == ljsde.EINVAL
+    # the code-pattern constructor refuses the weights marker
+    pat = np.zeros(4, np.uint8)
+    st = ljsde.lib().ljsde_plan(pat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), 2, 2, 32, 4, 10, 0.7, 0.5,
+                                ljsde.FP64 | ljsde.WEIGHTS)
+    assert st == ljsde.EINVAL
+
+
+def test_plan_weights_info_and_class_enumeration_follow_the_tile_period():
+    pid = ljsde.plan_weights(WTILE, window=32, block=4, iters=7)
+    info = ljsde.plan_info(pid)
+    assert info["flags"] & ljsde.WEIGHTS and info["flags"] & ljsde.DENSE_C and info["iters"] == 7
+    # a 3 x 4 tile has the class structure of any 3 x 4 code pattern
+    ref = ljsde.plan(random_pattern(3, 4, seed=1), window=32, block=4, fp64=True, dense_c=True)
+    for rows, cols in [(48, 64), (30, 44)]:
+        n1, c1 = ljsde.class_map(pid, rows, cols)
+        n2, c2 = ljsde.class_map(ref, rows, cols)
+        assert n1 == n2 and np.array_equal(c1, c2)
+    ljsde.release(pid)
+    ljsde.release(ref)
+
+
+@pytest.mark.parametrize("W,bi,bj", [(32, 10, 9), (32, 0, 3), (16, 1, 5), (16, 23, 0)])
+def test_weights_class_tables_reproduce_dense_C_and_D(W, bi, bj):
+    """For a general layout the library's ten spectra S_qq' and D rebuild the
+    oracle's dense C (eq. (14)) and D (eq. (13)) of the same local measurement
+    matrix: C(f, g) = sum_{q, q'} conj(e_q(f)) e_q'(g) S_qq'(f - g) with the
+    quadrant responses e_q(f) = exp(i theta (a sigma + b rho)), q = 2a + b."""
+    rows = cols = 96
+    pid = ljsde.plan_weights(WTILE, window=W, block=4)
+    n, cls = ljsde.class_map(pid, rows // 2, cols // 2)
+    c = int(cls[bi * (cols // 4) + bj])
+    S, D, codes = ljsde.class_tables(pid, rows // 2, cols // 2, c, W)
+    assert S.shape == ((W // 2) ** 2, 10)
+    y = np.zeros((rows // 2, cols // 2))
+    _, wloc, valid = O.local_window(y, WTILE, bi, bj, W, 4)
+    assert np.array_equal(codes >= 0, valid) and np.all(codes[valid] == 0)
+    A = O.local_measurement_operator_weights(wloc, valid, W)
+    a = O.basis_responses(A, O.fourier_basis(W))
+    w = O.spatial_weights(W, 0.7) * valid.reshape(-1)
+    _, C, Dref = O.rljsde_precompute(a, w)
+    np.testing.assert_allclose(D, Dref, rtol=1e-11)
+    Ws = W // 2
+    pairs = [(q, r) for q in range(4) for r in range(q, 4)]
+    Sq = np.zeros((4, 4, Ws, Ws), dtype=complex)
+    for k, (q, r) in enumerate(pairs):
+        Sq[q, r] = Sq[r, q] = S[:, k].reshape(Ws, Ws)
+    sg = np.arange(W * W) // W
+    rh = np.arange(W * W) % W
+    eq = np.stack([np.exp(2j * np.pi * ((q >> 1) * sg + (q & 1) * rh) / W) for q in range(4)])
+    dk = (sg[:, None] - sg[None, :]) % Ws
+    dl = (rh[:, None] - rh[None, :]) % Ws
+    Cf = sum(np.conj(eq[q])[:, None] * eq[r][None, :] * Sq[q, r][dk, dl] for q in range(4) for r in range(4))
+    np.testing.assert_allclose(Cf, C, atol=1e-11 * np.abs(C).max())
+    ljsde.release(pid)

@@ -1,0 +1,136 @@
+"""GPU parity for general layouts of the 2x2-footprint sensor (Sec. II, eq. (1):
+per-pixel quadrant weights; Sec. I: any recurrent layout), through the C ABI
+(``ljsde_plan_weights``, dense FP64 form), against the FP64 CPU oracle.
+
+Bar: <= 1e-9 max-abs and equal selection sequences (ties within a relative
+1e-10 go to the lowest frequency index on both sides). Layouts are chosen so
+that no frequency is annihilated by the sampling (D of eq. (13) bounded away
+from 0).
+"""
+import numpy as np
+import pytest
+
+from oracle import ljsde_oracle as O
+from synth import QUARTER, THREE_QUARTER, random_pattern, random_weights, sense_weights, shape_weights, \
+    synthetic_image
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_02646_amd import ljsde
+    ljsde.lib()
+    return ljsde
+
+
+def _dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).to("cuda:0")
+
+
+def _tile(kind, pr, pc, seed):
+    if kind == "random":
+        return random_weights(pr, pc, seed=seed)
+    if kind == "signed":  # weights of either sign (a difference-of-masks read-out)
+        return random_weights(pr, pc, seed=seed) - 0.35
+    if kind == "tq01":
+        return shape_weights(random_pattern(pr, pc, seed=seed), THREE_QUARTER)
+    if kind == "q01":
+        return shape_weights(random_pattern(pr, pc, seed=seed), QUARTER)
+    raise ValueError(kind)
+
+
+WCASES = {
+    # name: (rows, cols, (pr, pc) or None = whole sensor, kind, W, B, iters, rho, gamma, q_ones, seed)
+    "random_w32b4_ragged": (48, 40, (4, 4), "random", 32, 4, 30, 0.7, 0.5, False, 31),
+    "random_w16b8": (40, 56, (3, 5), "random", 16, 8, 30, 0.7, 0.5, False, 32),
+    "random_w16b4": (24, 40, (2, 3), "random", 16, 4, 40, 0.7, 0.5, False, 33),
+    "random_w32b8_qones": (40, 48, (4, 2), "random", 32, 8, 25, 0.6, 1.2, True, 34),
+    "signed_w32b4": (40, 40, (3, 3), "signed", 32, 4, 25, 0.7, 0.5, False, 35),
+    "random_nonrecurrent": (32, 32, None, "random", 32, 4, 40, 0.7, 0.5, False, 36),
+    "tq01_w32b4": (48, 40, (4, 4), "tq01", 32, 4, 30, 0.7, 0.5, False, 37),
+    "q01_w16b4": (40, 40, (4, 4), "q01", 16, 4, 30, 0.7, 0.5, False, 38),
+}
+
+
+def _case(name):
+    rows, cols, per, kind, W, B, iters, rho, gamma, q_ones, seed = WCASES[name]
+    pr, pc = (rows, cols) if per is None else per
+    wt = _tile(kind, pr, pc, seed)
+    _, f = synthetic_image(2 * rows, 2 * cols, seed=seed)
+    y = sense_weights(f, wt)
+    kw = dict(W=W, B=B, iters=iters, rho=rho, gamma=gamma, form="RL", q_mode="ones" if q_ones else "fsr")
+    ref, tr = O.reconstruct(y, None, traces=True, weights=wt, **kw)
+    return wt, y, ref, tr, dict(window=W, block=B, iters=iters, rho=rho, gamma=gamma, q_ones=q_ones)
+
+
+@pytest.mark.parametrize("name", list(WCASES))
+def test_weights_plan_matches_oracle(L, name):
+    wt, y, ref, tr, kw = _case(name)
+    pid = L.plan_weights(wt, **kw)
+    out, sel = L.reconstruct_diag(_dev(y, np.float64), pid)
+    out = out.cpu().numpy()
+    sel = sel.cpu().numpy()
+    err = np.max(np.abs(out - ref))
+    print(f"{name}: weights dense FP64 max-abs {err:.3e}", flush=True)
+    assert err <= FP64_TOL
+    nbj = out.shape[1] // kw["block"]
+    for w in range(sel.shape[0]):
+        assert list(sel[w]) == tr[divmod(w, nbj)].picks, w
+    # the call without selections runs the same kernel
+    out2 = L.reconstruct(_dev(y, np.float64), pid).cpu().numpy()
+    assert np.array_equal(out, out2)
+    L.release(pid)
+
+
+@pytest.mark.parametrize("shape", [THREE_QUARTER, QUARTER])
+def test_zero_one_weights_match_the_pixel_shape_plan(L, shape):
+    """0/1 weights of a code tile give that shape's measurement matrix, so the
+    weights plan and the code plan (dense FP64 form) reconstruct the same image
+    and select the same frequencies."""
+    rows, cols = 40, 48
+    tile = random_pattern(4, 4, seed=40 + shape)
+    _, f = synthetic_image(2 * rows, 2 * cols, seed=41)
+    y = sense_weights(f, shape_weights(tile, shape))
+    kw = dict(window=32, block=4, iters=40)
+    p_code = L.plan(tile, fp64=True, dense_c=True, shape=0 if shape == THREE_QUARTER else shape, **kw)
+    p_wt = L.plan_weights(shape_weights(tile, shape), **kw)
+    yd = _dev(y, np.float64)
+    a, sa = L.reconstruct_diag(yd, p_code)
+    b, sb = L.reconstruct_diag(yd, p_wt)
+    err = float((a - b).abs().max())
+    print(f"shape 0x{shape:x}: code plan vs weights plan max-abs {err:.3e}", flush=True)
+    assert err <= FP64_TOL
+    assert torch.equal(sa, sb)
+    L.release(p_code)
+    L.release(p_wt)
+
+
+def test_weights_plan_full_size_frame_sampled(L):
+    """A 512 x 512 frame (256 x 256 sensor) under a recurrent 4 x 4 general
+    layout, in the configuration the benchmark times: sampled target blocks
+    (corners, edges, interior) against the oracle, one window at a time."""
+    rows = cols = 256
+    wt = random_weights(4, 4, seed=50)
+    _, f = synthetic_image(2 * rows, 2 * cols, seed=50)
+    y = sense_weights(f, wt)
+    pid = L.plan_weights(wt, window=32, block=4, iters=100)
+    out, sel = L.reconstruct_diag(_dev(y, np.float64), pid)
+    out = out.cpu().numpy()
+    sel = sel.cpu().numpy()
+    nbi = nbj = 2 * rows // 4
+    rng = np.random.default_rng(50)
+    blocks = [(0, 0), (0, nbj - 1), (nbi - 1, 0), (nbi - 1, nbj - 1), (1, 2), (nbi // 2, 0)]
+    blocks += [tuple(int(v) for v in rng.integers(0, nbi, size=2)) for _ in range(10)]
+    ref, tr = O.reconstruct(y, None, W=32, B=4, iters=100, form="RL", blocks=blocks, traces=True, weights=wt)
+    for bi, bj in blocks:
+        blk = (slice(4 * bi, 4 * bi + 4), slice(4 * bj, 4 * bj + 4))
+        assert np.max(np.abs(out[blk] - ref[blk])) <= FP64_TOL, (bi, bj)
+        assert list(sel[bi * nbj + bj]) == tr[(bi, bj)].picks, (bi, bj)
+    assert np.all(np.isfinite(out))
+    L.release(pid)
