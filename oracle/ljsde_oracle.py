@@ -50,9 +50,16 @@ in the design notes of the repository):
 * q = (1 - |f~| / (sqrt(2) W / 2))^2 with the aliased frequency magnitude
   |f~| = sqrt(min(s, W-s)^2 + min(r, W-r)^2) (Sec. IV only says it prefers low
   frequencies); ``q_mode='ones'`` gives q = 1.
-* One complex coefficient per iteration, as in eqs. (15)-(17); frequencies
-  with D <= 0 get metric 0; the output is the real part of the central block
-  of eq. (18).
+* One complex coefficient per iteration, as in eqs. (15)-(17); the output is
+  the real part of the central block of eq. (18).
+* A frequency that leaves no trace in the window's measurements (every
+  response a_m(sigma, rho) is 0, so D of eqs. (10)/(13) is 0: e.g. rho = W/2
+  for pixels that integrate a horizontal pair of quadrants, or sigma = W/2 or
+  rho = W/2 for full pixels) has no defined step (eq. (16) divides by D). In
+  FP64 its D is rounding noise, some 1e-32 of the largest D, and its metric
+  would be noise divided by noise. Reading: a frequency whose D is at most
+  D_REL = 1e-13 times the largest D of the same local measurement matrix is
+  unobserved and gets metric 0 (never selected); D <= 0 likewise.
 * Ties in the argmax of eqs. (10)/(11) are left open by the paper. They are
   exact, not rare: conjugate partners tie whenever the residual is real, and
   a sparse pattern can make two basis functions alias (their measurement
@@ -254,6 +261,7 @@ class WindowTrace:
 
 
 TIE_REL = 1e-10
+D_REL = 1e-13
 
 
 def _select(metric: np.ndarray):
@@ -269,8 +277,9 @@ def _select(metric: np.ndarray):
 
 
 def _metric(q, R, D):
+    # q |R|^2 / D of eqs. (10)/(11); unobserved frequencies (D <= D_REL max D) get 0
     out = np.zeros(D.shape)
-    pos = D > 0
+    pos = (D > 0) & (D > D_REL * D.max())
     out[pos] = q[pos] * np.abs(R[pos]) ** 2 / D[pos]
     return out
 

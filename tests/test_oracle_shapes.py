@@ -161,3 +161,105 @@ def test_quarter_sampling_of_a_measurement_consistent_basis_function_is_recovere
     k = tr.picks[0]
     # the pick explains the measurements exactly
     np.testing.assert_allclose(a[:, k] * tr.coeffs[k], y_loc, atol=1e-9)
+
+
+def _unobserved_closed_form(shape, codes, W):
+    """Frequencies at which every present pixel's response vanishes: a pixel
+    of code o responds with exp(i theta (2i' sigma + 2j' rho)) times
+    sum_{d in mask} exp(i theta (qa sigma + qb rho)), q = o ^ d, and that sum
+    is 0 exactly where the collected quadrants pair off with opposite phases
+    (sigma or rho = W/2 for side-by-side pairs; sigma -/+ rho = W/2 for the
+    diagonal pairs; one of both for the full pixel)."""
+    s = np.arange(W)[:, None]
+    r = np.arange(W)[None, :]
+    h = W // 2
+    dead = np.ones((W, W), dtype=bool)
+    for o in set(int(c) for c in np.unique(codes)):
+        quads = sorted(o ^ d for d in range(4) if (shape >> d) & 1)
+        if quads == [0, 1] or quads == [2, 3]:
+            z = np.broadcast_to(r == h, (W, W))
+        elif quads == [0, 2] or quads == [1, 3]:
+            z = np.broadcast_to(s == h, (W, W))
+        elif quads == [0, 3]:
+            z = (s + r) % W == h
+        elif quads == [1, 2]:
+            z = (s - r) % W == h
+        elif quads == [0, 1, 2, 3]:
+            z = (s == h) | (r == h)
+        else:
+            z = np.zeros((W, W), dtype=bool)
+        dead &= z
+    return dead.reshape(-1)
+
+
+@pytest.mark.parametrize("shape", [0b0011, 0b0101, 0b1100, 0b0110, 0b1001, 0b1111, THREE_QUARTER, QUARTER])
+def test_unobserved_frequencies_are_exactly_the_closed_form_set(shape):
+    """Frequencies with no trace in the measurements get metric 0 whatever
+    the residual; all others keep their q |R|^2 / D."""
+    W = 16
+    rng = np.random.default_rng(shape + 30)
+    codes = rng.integers(0, 4, size=(W // 2, W // 2))
+    valid = np.ones_like(codes, dtype=bool)
+    A = O.local_measurement_operator(codes, valid, W, shape)
+    a = O.basis_responses(A, O.fourier_basis(W))
+    w = O.spatial_weights(W, 0.7)
+    D = (w[:, None] * np.abs(a) ** 2).sum(axis=0)
+    R = rng.normal(size=W * W) + 1j * rng.normal(size=W * W)
+    m = O._metric(np.ones(W * W), R, D)
+    dead = _unobserved_closed_form(shape, codes, W)
+    assert np.array_equal(m == 0, dead)
+    assert np.all(D[dead] < 1e-25 * D.max()) and np.all(D[~dead] > 1e-6 * D.max())
+
+
+@pytest.mark.parametrize("shape,W", [(0b0011, 8), (0b1111, 8), (0b0110, 16)])
+def test_half_and_full_pixel_selection_and_step_match_bruteforce_least_squares(shape, W):
+    """Pixels that integrate two quadrants, or all four: the pick is a
+    maximiser of the brute-force weighted least-squares gain over all basis
+    functions, and its step is the least-squares step."""
+    rng = np.random.default_rng(300 + shape + W)
+    codes = rng.integers(0, 4, size=(W // 2, W // 2))
+    valid = np.ones_like(codes, dtype=bool)
+    valid[1, 2] = False
+    f_win = rng.uniform(0, 255, size=(W, W))
+    A = O.local_measurement_operator(codes, valid, W, shape)
+    y_loc = np.tensordot(A, f_win, axes=([1, 2], [0, 1]))
+    w = O.spatial_weights(W, 0.7) * valid.reshape(-1)
+    q = O.frequency_weights(W, "fsr")
+    n = np.arange(W)
+    e = np.exp(2j * np.pi * np.outer(n, n) / W)
+    Psi = np.einsum("as,bt->abst", e, e)
+    a_ind = np.einsum("mab,abst->mst", A, Psi).reshape(A.shape[0], W * W)
+    a = O.basis_responses(A, O.fourier_basis(W))
+    sw = np.sqrt(w)
+    for nu in range(4):
+        tr = O.ljsde_window(y_loc, a, w, q, nu + 1, 0.5)
+        prev = O.ljsde_window(y_loc, a, w, q, nu, 0.5)
+        f_hat = np.einsum("abst,st->ab", Psi, prev.coeffs.reshape(W, W))
+        r = y_loc - np.tensordot(A, f_hat, axes=([1, 2], [0, 1]))
+        E = np.sum(w * np.abs(r) ** 2)
+        gains = np.zeros(W * W)
+        steps = np.zeros(W * W, dtype=complex)
+        for k in range(W * W):
+            col = sw * a_ind[:, k]
+            nrm = np.vdot(col, col).real
+            if nrm <= 1e-20 * np.sum(w) * 16:  # the column of an unobserved frequency: no gain
+                continue
+            d = np.vdot(col, sw * r) / nrm
+            steps[k] = d
+            gains[k] = E - np.sum(w * np.abs(r - d * a_ind[:, k]) ** 2)
+        k = tr.picks[-1]
+        score = q * gains
+        near = np.flatnonzero(score >= score.max() * (1 - 1e-9))
+        assert k in near
+        np.testing.assert_allclose(tr.r_pick[-1] / tr.d_pick[-1], steps[k], rtol=1e-9)
+
+
+@pytest.mark.parametrize("shape", [0b0011, 0b1111])
+def test_half_and_full_pixel_recurrent_equals_local_formulation(shape):
+    W, B = 16, 4
+    case = make_case(24, 32, 4, seed=14, shape=shape)
+    outL, trL = O.reconstruct(case["y"], case["tile"], W=W, B=B, iters=30, form="L", traces=True, shape=shape)
+    outR, trR = O.reconstruct(case["y"], case["tile"], W=W, B=B, iters=30, form="RL", traces=True, shape=shape)
+    assert np.max(np.abs(outL - outR)) <= 1e-10
+    for key in trL:
+        assert [_canon(k, W) for k in trL[key].picks] == [_canon(k, W) for k in trR[key].picks]
