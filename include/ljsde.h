@@ -77,11 +77,19 @@ enum {
  * matrix). Flag bits 8..11 hold a mask of quadrant offsets d: the sensor
  * pixel of code o collects light on the quadrants o XOR d (quadrant index
  * 2 * row + column inside its 2x2 footprint) for the bits d that are set.
- * 0 means three-quarter sampling. Kernels exist for three-quarter sampling
- * (L-shaped pixels, the code names the opaque quadrant) and quarter sampling
- * (the code names the one transparent quadrant); other masks are
- * LJSDE_EUNSUPPORTED, and so are LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32
- * with quarter sampling.
+ * 0 means three-quarter sampling (0xE: L-shaped pixels, the code names the
+ * opaque quadrant); 0x1 is quarter sampling (the code names the one
+ * transparent quadrant). The other masks with three or one bits are the same
+ * two layouts with relabelled codes and run on the same kernels (class
+ * tables then report the relabelled codes). Masks with two bits (half and
+ * diagonal pixels) or four (full pixels) run as their 0/1 quadrant weights on
+ * the general-layout dense form (see ljsde_plan_weights): they need
+ * LJSDE_FP64 | LJSDE_DENSE_C, else LJSDE_EUNSUPPORTED, and ljsde_plan_info
+ * reports LJSDE_WEIGHTS for them. LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32
+ * exist for three-quarter sampling only.
+ * Frequencies that no measurement of a window responds to (D of eq. (13) at
+ * most 1e-13 of the window's largest D: e.g. rho = W/2 for side-by-side
+ * quadrant pairs) are never selected.
  */
 #define LJSDE_SHAPE(mask) ((((unsigned)(mask)) & 15u) << 8)
 enum {
@@ -130,11 +138,9 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols,
  *            LJSDE_EUNSUPPORTED.
  * Per class the tables hold the ten spectra S_qq' = DFT(w A_q A_q') (q <= q')
  * and the per-pixel weights; C of eq. (14) is built from them on the device.
- * A layout under which some frequency leaves no trace in a window (D = 0 in
- * exact arithmetic, e.g. equal weights on all four quadrants at sigma = W/2)
- * makes eq. (11) decide on rounding noise there; such layouts are accepted,
- * but the selection at those frequencies is not reproducible across
- * implementations.
+ * Frequencies that leave no trace in a window (D of eq. (13) is 0 in exact
+ * arithmetic, e.g. equal weights on all four quadrants at sigma = W/2; in
+ * FP64 at most 1e-13 of the window's largest D) are never selected.
  * Returns a pattern id >= 0, or a negative status. Needs no GPU.
  */
 int ljsde_plan_weights(const double *weights, int pat_rows, int pat_cols,

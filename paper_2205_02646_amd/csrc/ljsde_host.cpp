@@ -225,13 +225,20 @@ void enumerate(const Plan &p, SizeSet &s) {
     }
 }
 
-// q / D, 1 / D (0 where D <= 0) of one class
+// A frequency whose D (eq. (13)) is at most D_REL times the class's largest
+// D has no response in any measurement of the window (its exact D is 0; the
+// computed one is rounding noise, eq. (16) is undefined): unobserved, metric 0.
+constexpr double D_REL = 1e-13;
+
+// q / D and 1 / D of one class, 0 at unobserved frequencies
 void store_normaliser(const Plan &p, const double *D, unsigned char *dst) {
     double *qd = (double *)(dst + p.lay.offQD64);
     double *inv = (double *)(dst + p.lay.offInvD);
     float *qd32 = (float *)(dst + p.lay.offQD32);
+    double dmax = 0.0;
+    for (int f = 0; f < p.W * p.W; ++f) dmax = std::max(dmax, D[f]);
     for (int f = 0; f < p.W * p.W; ++f) {
-        const bool pos = D[f] > 0;
+        const bool pos = D[f] > 0 && D[f] > D_REL * dmax;
         qd[f] = pos ? p.q[f] / D[f] : 0.0;
         inv[f] = pos ? 1.0 / D[f] : 0.0;
         qd32[f] = (float)qd[f];
@@ -358,21 +365,13 @@ void build_class(const Plan &p, const SizeSet &s, int cls, unsigned char *dst, d
             }
     double mass[4];
     for (int o = 0; o < 4; ++o) mass[o] = S[o * 2];  // S_o(0, 0)
-    double *qd = (double *)(dst + p.lay.offQD64);
-    double *inv = (double *)(dst + p.lay.offInvD);
-    float *qd32 = (float *)(dst + p.lay.offQD32);
-    for (int sg = 0; sg < W; ++sg)
-        for (int rh = 0; rh < W; ++rh) {
-            const int f = sg * W + rh;
-            const double *H = &p.H[(size_t)f * 8];
-            double D = 0;
-            for (int o = 0; o < 4; ++o) D += (H[2 * o] * H[2 * o] + H[2 * o + 1] * H[2 * o + 1]) * mass[o];
-            Dout[f] = D;
-            const bool pos = D > 0;
-            qd[f] = pos ? p.q[f] / D : 0.0;
-            inv[f] = pos ? 1.0 / D : 0.0;
-            qd32[f] = (float)qd[f];
-        }
+    for (int f = 0; f < W * W; ++f) {
+        const double *H = &p.H[(size_t)f * 8];
+        double D = 0;
+        for (int o = 0; o < 4; ++o) D += (H[2 * o] * H[2 * o] + H[2 * o + 1] * H[2 * o + 1]) * mass[o];
+        Dout[f] = D;
+    }
+    store_normaliser(p, Dout, dst);
     signed char *cd = (signed char *)(dst + p.lay.offCodes);
     for (int m = 0; m < Ws * Ws; ++m) cd[m] = (signed char)code[m];
 }
@@ -916,15 +915,36 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, i
     if (!(block == 4 || block == 8))
         return fail(LJSDE_EUNSUPPORTED, "no kernel for block %d (have 4, 8)", block);
     if (iters > 32767) return fail(LJSDE_EUNSUPPORTED, "iters %d above 32767", iters);
-    int shape = (int)((flags >> 8) & 15u);
-    if (shape == 0) shape = 0xE;
-    if (shape != 0xE && shape != 0x1)
-        return fail(LJSDE_EUNSUPPORTED,
-                    "pixel shape mask 0x%x: kernels exist for three-quarter (0xE) and quarter (0x1) sampling", shape);
-    if (shape == 0x1 && (flags & (LJSDE_DFT_SPLITBF16 | LJSDE_STATE_FP32)))
-        return fail(LJSDE_EUNSUPPORTED, "LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32 exist for three-quarter sampling only");
+    int mask = (int)((flags >> 8) & 15u);
+    if (mask == 0) mask = 0xE;
+    const int bits = __builtin_popcount(mask);
     auto p = std::make_unique<Plan>();
-    p->pattern.assign(pattern, pattern + (size_t)pat_rows * pat_cols);
+    const size_t n = (size_t)pat_rows * pat_cols;
+    p->pattern.assign(pattern, pattern + n);
+    if (bits == 3 || bits == 1) {
+        // Three collected quadrants: the pixel of code o misses o ^ d for the
+        // one offset d outside the mask, i.e. three-quarter sampling with the
+        // opaque quadrant o ^ d. One collected quadrant o ^ d: quarter
+        // sampling with the transparent quadrant o ^ d. Relabel the codes.
+        const int d = __builtin_ctz(bits == 3 ? (~mask & 15) : mask);
+        for (auto &c : p->pattern) c = (uint8_t)(c ^ d);
+        p->shape = bits == 3 ? 0xE : 0x1;
+        if (p->shape == 0x1 && (flags & (LJSDE_DFT_SPLITBF16 | LJSDE_STATE_FP32)))
+            return fail(LJSDE_EUNSUPPORTED,
+                        "LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32 exist for three-quarter sampling only");
+        p->flags = flags;
+    } else {
+        // Two or four collected quadrants (half, diagonal and full pixels):
+        // their 0/1 quadrant weights through the general-layout dense form.
+        if ((flags & (LJSDE_FP64 | LJSDE_DENSE_C)) != (LJSDE_FP64 | LJSDE_DENSE_C))
+            return fail(LJSDE_EUNSUPPORTED,
+                        "pixel shape mask 0x%x runs on the dense FP64 form only (LJSDE_FP64 | LJSDE_DENSE_C)", mask);
+        p->quad.resize(n * 4);
+        for (size_t i = 0; i < n; ++i)
+            for (int q = 0; q < 4; ++q) p->quad[i * 4 + q] = (double)((mask >> (q ^ pattern[i])) & 1);
+        p->shape = SHAPE_GENERAL;
+        p->flags = flags | LJSDE_WEIGHTS;
+    }
     p->pr = pat_rows;
     p->pc = pat_cols;
     p->W = window;
@@ -932,8 +952,6 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, i
     p->iters = iters;
     p->rho = rho;
     p->gamma = gamma;
-    p->flags = flags;
-    p->shape = shape;
     return register_plan(std::move(p));
 }
 

@@ -56,8 +56,10 @@ TILE = random_pattern(4, 4, seed=0)
     (dict(splitbf16=True, state_fp32=True), ljsde.EUNSUPPORTED),
     (dict(splitbf16=True, window=16), ljsde.EUNSUPPORTED),
     (dict(dense_c=True), ljsde.EINVAL),          # the dense form exists for FP64 plans
-    (dict(shape=0x3), ljsde.EUNSUPPORTED),      # a valid shape with no kernel
+    (dict(shape=0x3), ljsde.EUNSUPPORTED),      # half pixels: dense FP64 form only
     (dict(shape=0xF), ljsde.EUNSUPPORTED),
+    (dict(shape=0x6, fp64=True), ljsde.EUNSUPPORTED),
+    (dict(shape=0x4, splitbf16=True), ljsde.EUNSUPPORTED),   # a relabelled quarter sampling
     (dict(shape=ljsde.SHAPE_QUARTER, splitbf16=True), ljsde.EUNSUPPORTED),
     (dict(shape=ljsde.SHAPE_QUARTER, state_fp32=True), ljsde.EUNSUPPORTED),
 ])
@@ -348,4 +350,61 @@ def test_weights_class_tables_reproduce_dense_C_and_D(W, bi, bj):
     dl = (rh[:, None] - rh[None, :]) % Ws
     Cf = sum(np.conj(eq[q])[:, None] * eq[r][None, :] * Sq[q, r][dk, dl] for q in range(4) for r in range(4))
     np.testing.assert_allclose(Cf, C, atol=1e-11 * np.abs(C).max())
+    ljsde.release(pid)
+
+
+@pytest.mark.parametrize("mask,kernel_shape,d", [(0x7, 0xE, 3), (0xB, 0xE, 2), (0xD, 0xE, 1),
+                                                  (0x2, 0x1, 1), (0x4, 0x1, 2), (0x8, 0x1, 3)])
+def test_three_and_one_quadrant_masks_are_relabelled_layouts(mask, kernel_shape, d):
+    """Three collected quadrants are three-quarter sampling with the opaque
+    quadrant o ^ d (d the offset outside the mask); one collected quadrant o ^ d
+    is quarter sampling with that transparent quadrant: the plan's tables equal
+    those of the relabelled code tile, and its D equals the oracle's D of the
+    original codes under the original mask."""
+    tile = random_pattern(4, 4, seed=mask)
+    W, rows, cols = 32, 96, 96
+    p1 = ljsde.plan(tile, window=W, block=4, fp64=True, shape=mask)
+    p2 = ljsde.plan(tile ^ d, window=W, block=4, fp64=True, shape=kernel_shape)
+    n1, c1 = ljsde.class_map(p1, rows // 2, cols // 2)
+    n2, c2 = ljsde.class_map(p2, rows // 2, cols // 2)
+    assert n1 == n2 and np.array_equal(c1, c2)
+    for c in range(n1):
+        t1 = ljsde.class_tables(p1, rows // 2, cols // 2, c, W)
+        t2 = ljsde.class_tables(p2, rows // 2, cols // 2, c, W)
+        for a, b in zip(t1, t2):
+            assert np.array_equal(a, b)
+    bi, bj = 10, 9
+    c = int(c1[bi * (cols // 4) + bj])
+    _, D, _ = ljsde.class_tables(p1, rows // 2, cols // 2, c, W)
+    _, ocodes, valid = O.local_window(np.zeros((rows // 2, cols // 2)), tile, bi, bj, W, 4)
+    A = O.local_measurement_operator(ocodes, valid, W, mask)
+    a = O.basis_responses(A, O.fourier_basis(W))
+    _, _, Dref = O.rljsde_precompute(a, O.spatial_weights(W, 0.7) * valid.reshape(-1))
+    np.testing.assert_allclose(D, Dref, rtol=1e-12)
+    assert (ljsde.plan_info(p1)["flags"] >> 8) & 15 == mask
+    ljsde.release(p1)
+    ljsde.release(p2)
+
+
+@pytest.mark.parametrize("mask", [0x3, 0x5, 0x6, 0x9, 0xA, 0xC, 0xF])
+def test_two_and_four_quadrant_masks_run_as_weights_plans(mask):
+    """Half, diagonal and full pixels become 0/1 quadrant weights on the dense
+    FP64 form: their D rebuilds the oracle's D of the same codes and mask
+    (absolutely, relative to the largest D: at the unobserved frequencies both
+    are rounding noise)."""
+    tile = random_pattern(4, 4, seed=mask + 7)
+    W, rows, cols = 16, 48, 64
+    pid = ljsde.plan(tile, window=W, block=4, fp64=True, dense_c=True, shape=mask)
+    info = ljsde.plan_info(pid)
+    assert info["flags"] & ljsde.WEIGHTS and (info["flags"] >> 8) & 15 == mask
+    n, cls = ljsde.class_map(pid, rows // 2, cols // 2)
+    for bi, bj in [(0, 0), (5, 7), (11, 15)]:
+        c = int(cls[bi * (cols // 4) + bj])
+        S, D, codes = ljsde.class_tables(pid, rows // 2, cols // 2, c, W)
+        assert S.shape[1] == 10
+        _, ocodes, valid = O.local_window(np.zeros((rows // 2, cols // 2)), tile, bi, bj, W, 4)
+        A = O.local_measurement_operator(ocodes, valid, W, mask)
+        a = O.basis_responses(A, O.fourier_basis(W))
+        _, _, Dref = O.rljsde_precompute(a, O.spatial_weights(W, 0.7) * valid.reshape(-1))
+        np.testing.assert_allclose(D, Dref, rtol=0, atol=1e-12 * Dref.max())
     ljsde.release(pid)

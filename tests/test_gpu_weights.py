@@ -1,23 +1,24 @@
 """GPU parity for general layouts of the 2x2-footprint sensor (Sec. II, eq. (1):
-per-pixel quadrant weights; Sec. I: any recurrent layout), through the C ABI
-(``ljsde_plan_weights``, dense FP64 form), against the FP64 CPU oracle.
+per-pixel quadrant weights; Sec. I: any recurrent layout) and for every
+pixel-shape mask, through the C ABI, against the FP64 CPU oracle.
 
-Bar: <= 1e-9 max-abs and equal selection sequences (ties within a relative
-1e-10 go to the lowest frequency index on both sides). Layouts are chosen so
-that no frequency is annihilated by the sampling (D of eq. (13) bounded away
-from 0).
+Bar: FP64 <= 1e-9 max-abs, FP32 <= 0.05 grey levels, and equal selection
+sequences (ties within a relative 1e-10 go to the lowest frequency index on
+both sides; frequencies without any measurement response are never
+selected).
 """
 import numpy as np
 import pytest
 
 from oracle import ljsde_oracle as O
-from synth import QUARTER, THREE_QUARTER, random_pattern, random_weights, sense_weights, shape_weights, \
-    synthetic_image
+from synth import QUARTER, THREE_QUARTER, make_case, random_pattern, random_weights, sense_weights, \
+    shape_weights, synthetic_image
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-9
+FP32_TOL = 0.05
 
 
 @pytest.fixture(scope="module")
@@ -134,3 +135,61 @@ def test_weights_plan_full_size_frame_sampled(L):
         assert list(sel[bi * nbj + bj]) == tr[(bi, bj)].picks, (bi, bj)
     assert np.all(np.isfinite(out))
     L.release(pid)
+
+
+MASK_CASES = {
+    # name: (rows, cols, period, W, B, iters, seed, mask)
+    "mask7_w32b4": (48, 40, 4, 32, 4, 30, 61, 0x7),    # three quadrants: relabelled three-quarter
+    "maskB_w16b8": (40, 56, 4, 16, 8, 30, 62, 0xB),
+    "mask4_w32b4": (40, 40, 4, 32, 4, 30, 63, 0x4),    # one quadrant: relabelled quarter
+    "half3_w32b4": (48, 40, 4, 32, 4, 30, 64, 0x3),    # horizontal pairs
+    "halfA_w16b4": (40, 40, 2, 16, 4, 30, 65, 0xA),    # vertical pairs
+    "diag6_w32b8": (40, 48, 4, 32, 8, 25, 66, 0x6),    # diagonal pairs
+    "full_w32b4": (40, 40, 4, 32, 4, 25, 67, 0xF),     # full pixels
+}
+
+
+def _mask_case(name):
+    rows, cols, per, W, B, iters, seed, mask = MASK_CASES[name]
+    c = make_case(rows, cols, per, seed=seed, shape=mask)
+    kw = dict(W=W, B=B, iters=iters, form="RL", shape=mask)
+    ref, tr = O.reconstruct(c["y"], c["tile"], traces=True, **kw)
+    return c, ref, tr, dict(window=W, block=B, iters=iters, shape=mask)
+
+
+def _check(out, sel, ref, tr, B, tol, label):
+    out = out.cpu().numpy().astype(np.float64)
+    sel = sel.cpu().numpy()
+    err = np.max(np.abs(out - ref))
+    print(f"{label}: max-abs {err:.3e}", flush=True)
+    assert err <= tol
+    nbj = out.shape[1] // B
+    for w in range(sel.shape[0]):
+        assert list(sel[w]) == tr[divmod(w, nbj)].picks, w
+
+
+@pytest.mark.parametrize("name", list(MASK_CASES))
+def test_every_pixel_shape_matches_oracle(L, name):
+    """Masks with three or one collected quadrants run on the three-quarter and
+    quarter kernels with relabelled codes (FP64 factorised and dense, FP32);
+    two or four collected quadrants run on the general-layout dense form."""
+    c, ref, tr, kw = _mask_case(name)
+    mask = kw["shape"]
+    relabelled = bin(mask).count("1") in (1, 3)
+    forms = [dict(fp64=True, dense_c=True)] + ([dict(fp64=True)] if relabelled else [])
+    for f in forms:
+        pid = L.plan(c["tile"], **f, **kw)
+        out, sel = L.reconstruct_diag(_dev(c["y"], np.float64), pid)
+        _check(out, sel, ref, tr, kw["block"], FP64_TOL, f"{name} FP64 {'dense' if 'dense_c' in f else 'factorised'}")
+        L.release(pid)
+    if relabelled:
+        y32 = c["y"].astype(np.float32)
+        ref32, tr32 = O.reconstruct(y32.astype(np.float64), c["tile"], traces=True, W=kw["window"],
+                                    B=kw["block"], iters=kw["iters"], form="RL", shape=mask)
+        pid = L.plan(c["tile"], **kw)
+        out, sel = L.reconstruct_diag(_dev(y32, np.float32), pid)
+        _check(out, sel, ref32, tr32, kw["block"], FP32_TOL, f"{name} FP32")
+        L.release(pid)
+    else:
+        with pytest.raises(L.LjsdeError):
+            L.plan(c["tile"], **kw)
