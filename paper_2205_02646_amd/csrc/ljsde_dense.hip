@@ -124,13 +124,54 @@ __global__ __launch_bounds__(256) void dense_c_build_general_kernel(KParams p, c
     }
 }
 
-// LDS of one wavefront: w*y [NPOS] FP64, codes [NPOS], and the VALU DFT's
-// stage [NPOS][4] complex for WS = 8 only
+// DPP lane move of a 64-bit value inside rows of 16 lanes (quad_perm and
+// mirror controls only: every source lane is valid).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_min_fill(unsigned v) {
+    return (unsigned)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
+}
+
+// Wavefront maximum of a nonnegative double: within rows of 16 by DPP (quad
+// xor 1, quad xor 2, half-row mirror, row mirror leave every lane with its
+// row's maximum), then across the four rows. Uniform result.
+__device__ __forceinline__ double wave_max_nonneg_f64(double v) {
+    v = fmax(v, dpp_f64<DPP_QUAD_XOR1>(v));
+    v = fmax(v, dpp_f64<DPP_QUAD_XOR2>(v));
+    v = fmax(v, dpp_f64<DPP_ROW_HALF_MIRROR>(v));
+    v = fmax(v, dpp_f64<DPP_ROW_MIRROR>(v));
+    const double a = readlane_f64(v, 0), b = readlane_f64(v, 16), c = readlane_f64(v, 32), d = readlane_f64(v, 48);
+    return fmax(fmax(a, b), fmax(c, d));
+}
+
+// Wavefront minimum of an unsigned value, same scheme. Uniform result.
+__device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
+    v = min(v, dpp_min_fill<DPP_QUAD_XOR1>(v));
+    v = min(v, dpp_min_fill<DPP_QUAD_XOR2>(v));
+    v = min(v, dpp_min_fill<DPP_ROW_HALF_MIRROR>(v));
+    v = min(v, dpp_min_fill<DPP_ROW_MIRROR>(v));
+    const unsigned a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+    const unsigned c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+    return min(min(a, b), min(c, d));
+}
+
+// LDS of one wavefront. Prologue: w*y [NPOS] FP64, codes [NPOS], and the VALU
+// DFT's stage [NPOS][4] complex for WS = 8 only. Loop: q / D of the class in
+// lane order [W^2] FP64 (entry (4t + c) * 64 + L), over the prologue's bytes.
 template <int WS>
 struct DenseLds {
     static constexpr int NPOS = WS * WS;
     static constexpr size_t stage = WS == 16 ? 0 : (size_t)NPOS * 8 * 8;
-    static constexpr size_t bytes = stage + (size_t)NPOS * 8 + NPOS;
+    static constexpr size_t prologue = stage + (size_t)NPOS * 8 + NPOS;
+    static constexpr size_t qd = (size_t)4 * WS * WS * 8;
+    static constexpr size_t bytes = prologue > qd ? prologue : qd;
 };
 
 // One wavefront per window. SHAPE is a pixel-shape mask or SHAPE_GENERAL
@@ -167,7 +208,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void de
     const double *ew = p.c.ew;
     const C2<double> tl = {ew[2 * lam], -ew[2 * lam + 1]};
     C2<double> R[QPL][4];
-    double qd[QPL][4];
+    double *ldsQ = (double *)lds;  // after the prologue
 #pragma unroll
     for (int t = 0; t < QPL; ++t) {
         const int kap = krow + KSTEP * t;
@@ -175,7 +216,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void de
         const C2<double> tkl = {ew[2 * (kap + lam)], -ew[2 * (kap + lam) + 1]};
         project4<double, PSHAPE>(P[t], tl, tk, tkl, R[t]);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) qd[t][c] = qD64[dense_freq<WS>(lane, t, c)];
+        for (int c = 0; c < 4; ++c) ldsQ[(4 * t + c) * 64 + lane] = qD64[dense_freq<WS>(lane, t, c)];
     }
 
     const double2 *Cc = Cd + (size_t)cls * NF * NF;
@@ -187,49 +228,62 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void de
 
 #pragma unroll 1
     for (int nu = 0; nu < p.iters; ++nu) {
-        // eq. (11): q |R|^2 / D, first maximum in sigma * W + rho order (ties
-        // within TIE_REL go to the lowest index). a = 0 and a = 1 frequencies
-        // are kept apart: all a = 1 indices exceed all a = 0 ones.
-        double best0 = -1.0, best1 = -1.0;
-        int code0 = 0, code1 = 0;
+        // eq. (11): q |R|^2 / D. The first maximum in sigma * W + rho order,
+        // ties within TIE_REL included: the lowest index whose metric reaches
+        // M (1 - TIE_REL), M the wavefront maximum. Within a lane the index
+        // grows with (a, t, b) for c = 2a + b.
+        int lq = lane;
+        asm volatile("" : "+v"(lq));  // q / D is re-read from LDS every iteration, not held in registers
+        double m[QPL][4];
+        double lmax = 0.0;
 #pragma unroll
-        for (int t = 0; t < QPL; ++t) {
+        for (int t = 0; t < QPL; ++t)
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const double m = (R[t][c].re * R[t][c].re + R[t][c].im * R[t][c].im) * qd[t][c];
-                if (c < 2) tie_keep<double>(best0, code0, m, 4 * t + c, TIE_REL);
-                else tie_keep<double>(best1, code1, m, 4 * t + c, TIE_REL);
+                m[t][c] = (R[t][c].re * R[t][c].re + R[t][c].im * R[t][c].im) * ldsQ[(4 * t + c) * 64 + lq];
+                lmax = fmax(lmax, m[t][c]);
             }
-        }
-        double best = best0;
-        int idx = dense_freq<WS>(lane, code0 >> 2, code0 & 3);
-        tie_merge<double>(best, idx, best1, dense_freq<WS>(lane, code1 >> 2, code1 & 3), TIE_REL);
-        for (int o = 32; o > 0; o >>= 1) {
-            const double ob = __shfl_xor(best, o);
-            const int oid = __shfl_xor(idx, o);
-            tie_merge<double>(best, idx, ob, oid, TIE_REL);
-        }
-        idx = __builtin_amdgcn_readfirstlane(idx);
+        const double thr = wave_max_nonneg_f64(lmax) * (1.0 - TIE_REL);
+        // rank r = 8a + 2t + b orders this lane's indices
+        int rank = 16;
+#pragma unroll
+        for (int a = 1; a >= 0; --a)
+#pragma unroll
+            for (int t = QPL - 1; t >= 0; --t)
+#pragma unroll
+                for (int b = 1; b >= 0; --b)
+                    if (m[t][2 * a + b] >= thr) rank = 8 * a + 2 * t + b;
+        // own index of rank r: (krow + KSTEP t + WS a) W + lam + WS b
+        const int ra = rank >> 3, rt = (rank >> 1) & 3, rb = rank & 1;
+        const unsigned fidx =
+            rank == 16 ? 0xFFFFFFFFu : (unsigned)((krow + KSTEP * rt + WS * ra) * W + lam + WS * rb);
+        const int idx = (int)wave_min_u32(fidx);
         const int u = idx / W, v = idx % W;
 
-        // R_uv from its owner lane
+        // eq. (17) needs column (u, v) of C: start its loads now
+        const double2 *col = Cc + (size_t)idx * NF + lane;
+        double2 cv[QPL][4];
+#pragma unroll
+        for (int t = 0; t < QPL; ++t)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cv[t][c] = col[(4 * t + c) * 64];
+        const double id = invD[idx];
+
+        // R_uv from its owner lane (uniform branch on the owner's register)
         const int ku = u % WS, lv = v % WS;
-        const int tu = ku / KSTEP, cu = 2 * (u / WS) + v / WS;
+        const int code = 4 * (ku / KSTEP) + 2 * (u / WS) + v / WS;
         const int owner = (ku % KSTEP) * WS + lv;
         double rr = 0.0, ri = 0.0;
 #pragma unroll
         for (int t = 0; t < QPL; ++t)
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                if (tu == t && cu == c) {
-                    rr = R[t][c].re;
-                    ri = R[t][c].im;
+                if (code == 4 * t + c) {
+                    rr = readlane_f64(R[t][c].re, owner);
+                    ri = readlane_f64(R[t][c].im, owner);
                 }
-        rr = readlane_f64(rr, owner);
-        ri = readlane_f64(ri, owner);
 
         // eqs. (15)-(16) and the energy of eq. (8)
-        const double id = invD[idx];
         const double gr = p.gamma * rr * id, gi = p.gamma * ri * id;
         E = uniform_f64(E - p.ecoef * (rr * rr + ri * ri) * id);
         // eq. (18) on the central block, pick by pick
@@ -242,14 +296,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void de
         if (p.tau > 0.0 && E <= p.tau * e0) break;
 
         // eq. (17): R -= gamma delta C(:, (u, v))
-        const double2 *col = Cc + (size_t)idx * NF + lane;
 #pragma unroll
         for (int t = 0; t < QPL; ++t)
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const double2 cv = col[(4 * t + c) * 64];
-                R[t][c].re -= gr * cv.x - gi * cv.y;
-                R[t][c].im -= gr * cv.y + gi * cv.x;
+                R[t][c].re -= gr * cv[t][c].x - gi * cv[t][c].y;
+                R[t][c].im -= gr * cv[t][c].y + gi * cv[t][c].x;
             }
     }
     if (j.sel != nullptr)
