@@ -124,44 +124,6 @@ __global__ __launch_bounds__(256) void dense_c_build_general_kernel(KParams p, c
     }
 }
 
-// DPP lane move of a 64-bit value inside rows of 16 lanes (quad_perm and
-// mirror controls only: every source lane is valid).
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-    const unsigned long long b = __double_as_longlong(v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, true);
-    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
-    return __longlong_as_double(((unsigned long long)hi << 32) | lo);
-}
-
-template <int CTRL>
-__device__ __forceinline__ unsigned dpp_min_fill(unsigned v) {
-    return (unsigned)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
-}
-
-// Wavefront maximum of a nonnegative double: within rows of 16 by DPP (quad
-// xor 1, quad xor 2, half-row mirror, row mirror leave every lane with its
-// row's maximum), then across the four rows. Uniform result.
-__device__ __forceinline__ double wave_max_nonneg_f64(double v) {
-    v = fmax(v, dpp_f64<DPP_QUAD_XOR1>(v));
-    v = fmax(v, dpp_f64<DPP_QUAD_XOR2>(v));
-    v = fmax(v, dpp_f64<DPP_ROW_HALF_MIRROR>(v));
-    v = fmax(v, dpp_f64<DPP_ROW_MIRROR>(v));
-    const double a = readlane_f64(v, 0), b = readlane_f64(v, 16), c = readlane_f64(v, 32), d = readlane_f64(v, 48);
-    return fmax(fmax(a, b), fmax(c, d));
-}
-
-// Wavefront minimum of an unsigned value, same scheme. Uniform result.
-__device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
-    v = min(v, dpp_min_fill<DPP_QUAD_XOR1>(v));
-    v = min(v, dpp_min_fill<DPP_QUAD_XOR2>(v));
-    v = min(v, dpp_min_fill<DPP_ROW_HALF_MIRROR>(v));
-    v = min(v, dpp_min_fill<DPP_ROW_MIRROR>(v));
-    const unsigned a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
-    const unsigned c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
-    return min(min(a, b), min(c, d));
-}
-
 // LDS of one wavefront. Prologue: w*y [NPOS] FP64, codes [NPOS], and the VALU
 // DFT's stage [NPOS][4] complex for WS = 8 only. Loop: q / D of the class in
 // lane order [W^2] FP64 (entry (4t + c) * 64 + L), over the prologue's bytes.
@@ -235,29 +197,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void de
         int lq = lane;
         asm volatile("" : "+v"(lq));  // q / D is re-read from LDS every iteration, not held in registers
         double m[QPL][4];
-        double lmax = 0.0;
 #pragma unroll
         for (int t = 0; t < QPL; ++t)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
+            for (int c = 0; c < 4; ++c)
                 m[t][c] = (R[t][c].re * R[t][c].re + R[t][c].im * R[t][c].im) * ldsQ[(4 * t + c) * 64 + lq];
-                lmax = fmax(lmax, m[t][c]);
-            }
-        const double thr = wave_max_nonneg_f64(lmax) * (1.0 - TIE_REL);
-        // rank r = 8a + 2t + b orders this lane's indices
-        int rank = 16;
-#pragma unroll
-        for (int a = 1; a >= 0; --a)
-#pragma unroll
-            for (int t = QPL - 1; t >= 0; --t)
-#pragma unroll
-                for (int b = 1; b >= 0; --b)
-                    if (m[t][2 * a + b] >= thr) rank = 8 * a + 2 * t + b;
-        // own index of rank r: (krow + KSTEP t + WS a) W + lam + WS b
-        const int ra = rank >> 3, rt = (rank >> 1) & 3, rb = rank & 1;
-        const unsigned fidx =
-            rank == 16 ? 0xFFFFFFFFu : (unsigned)((krow + KSTEP * rt + WS * ra) * W + lam + WS * rb);
-        const int idx = (int)wave_min_u32(fidx);
+        const int idx = select_lowest_max<double, WS, QPL>(m, TIE_REL, lane);
         const int u = idx / W, v = idx % W;
 
         // eq. (17) needs column (u, v) of C: start its loads now

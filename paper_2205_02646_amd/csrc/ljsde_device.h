@@ -306,4 +306,88 @@ __device__ __forceinline__ double readlane_f64(double x, int lane) {
     return __longlong_as_double(((unsigned long long)hi << 32) | lo);
 }
 
+// DPP lane move of a 64-bit value inside rows of 16 lanes (quad_perm and
+// mirror controls only: every source lane is valid).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_min_fill(unsigned v) {
+    return (unsigned)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Wavefront maximum of a nonnegative value: within rows of 16 by DPP (quad
+// xor 1, quad xor 2, half-row mirror, row mirror leave every lane with its
+// row's maximum), then across the four rows. Uniform result.
+__device__ __forceinline__ double wave_max_nonneg(double v) {
+    v = fmax(v, dpp_f64<DPP_QUAD_XOR1>(v));
+    v = fmax(v, dpp_f64<DPP_QUAD_XOR2>(v));
+    v = fmax(v, dpp_f64<DPP_ROW_HALF_MIRROR>(v));
+    v = fmax(v, dpp_f64<DPP_ROW_MIRROR>(v));
+    const double a = readlane_f64(v, 0), b = readlane_f64(v, 16), c = readlane_f64(v, 32), d = readlane_f64(v, 48);
+    return fmax(fmax(a, b), fmax(c, d));
+}
+
+__device__ __forceinline__ float wave_max_nonneg(float v) {
+    v = fmaxf(v, dpp_f32<DPP_QUAD_XOR1>(v));
+    v = fmaxf(v, dpp_f32<DPP_QUAD_XOR2>(v));
+    v = fmaxf(v, dpp_f32<DPP_ROW_HALF_MIRROR>(v));
+    v = fmaxf(v, dpp_f32<DPP_ROW_MIRROR>(v));
+    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return fmaxf(fmaxf(a, b), fmaxf(c, d));
+}
+
+// Wavefront minimum of an unsigned value, same scheme. Uniform result.
+__device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
+    v = min(v, dpp_min_fill<DPP_QUAD_XOR1>(v));
+    v = min(v, dpp_min_fill<DPP_QUAD_XOR2>(v));
+    v = min(v, dpp_min_fill<DPP_ROW_HALF_MIRROR>(v));
+    v = min(v, dpp_min_fill<DPP_ROW_MIRROR>(v));
+    const unsigned a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+    const unsigned c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+    return min(min(a, b), min(c, d));
+}
+
+// Selection of eqs. (10)/(11) over the metrics m[t][c] of a wavefront whose
+// lane L holds the frequencies ((L / WS + (64 / WS) t + WS a) W + L % WS + WS b,
+// c = 2a + b, t < QPL): the lowest index whose metric reaches M (1 - eps), M
+// the wavefront maximum (eps = TIE_REL: ties within TIE_REL go to the lowest
+// index; eps = 0: the first maximum). Metrics are nonnegative. Uniform result.
+template <typename T, int WS, int QPL>
+__device__ __forceinline__ int select_lowest_max(const T m[][4], T eps, int lane) {
+    constexpr int W = 2 * WS, KSTEP = 64 / WS;
+    T lmax = T(0);
+#pragma unroll
+    for (int t = 0; t < QPL; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) lmax = fmax(lmax, m[t][c]);
+    const T thr = wave_max_nonneg(lmax) * (T(1) - eps);
+    // rank r = 8a + 2t + b orders this lane's indices
+    int rank = 16;
+#pragma unroll
+    for (int a = 1; a >= 0; --a)
+#pragma unroll
+        for (int t = QPL - 1; t >= 0; --t)
+#pragma unroll
+            for (int b = 1; b >= 0; --b)
+                if (m[t][2 * a + b] >= thr) rank = 8 * a + 2 * t + b;
+    const int ra = rank >> 3, rt = (rank >> 1) & 3, rb = rank & 1;
+    const unsigned fidx = rank == 16 ? 0xFFFFFFFFu
+                                     : (unsigned)((lane / WS + KSTEP * rt + WS * ra) * W + lane % WS + WS * rb);
+    return (int)wave_min_u32(fidx);
+}
+
 }  // namespace ljsde

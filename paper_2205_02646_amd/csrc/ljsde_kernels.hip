@@ -104,8 +104,7 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
 
 #pragma unroll 1
     for (int nu = 0; nu < p.iters; ++nu) {
-        T best0 = T(-1), best1 = T(-1);
-        int code0 = 0, code1 = 0;
+        T m[QPL][4];
 #pragma unroll
         for (int t = 0; t < QPL; ++t) {
             const int kap = krow + KSTEP * t;
@@ -135,26 +134,14 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
             const C2<T> r01 = {d1.re - d2.re, d1.im - d2.im};
             const C2<T> r10 = {d1.re + d2.re, d1.im + d2.im};
             const C2<T> r11 = {s1.re - s2.re, s1.im - s2.im};
-            // eq. (11) metric q |R|^2 / D; first maximum in sigma * W + rho order
-            const T m00 = (r00.re * r00.re + r00.im * r00.im) * qd[t][0];
-            const T m01 = (r01.re * r01.re + r01.im * r01.im) * qd[t][1];
-            const T m10 = (r10.re * r10.re + r10.im * r10.im) * qd[t][2];
-            const T m11 = (r11.re * r11.re + r11.im * r11.im) * qd[t][3];
-            tie_keep<T>(best0, code0, m00, 2 * t, eps);
-            tie_keep<T>(best0, code0, m01, 2 * t + 1, eps);
-            tie_keep<T>(best1, code1, m10, 2 * t, eps);
-            tie_keep<T>(best1, code1, m11, 2 * t + 1, eps);
+            // eq. (11) metric q |R|^2 / D
+            m[t][0] = (r00.re * r00.re + r00.im * r00.im) * qd[t][0];
+            m[t][1] = (r01.re * r01.re + r01.im * r01.im) * qd[t][1];
+            m[t][2] = (r10.re * r10.re + r10.im * r10.im) * qd[t][2];
+            m[t][3] = (r11.re * r11.re + r11.im * r11.im) * qd[t][3];
         }
-        // a = 1 frequencies have higher indices than all a = 0 ones
-        T best = best0;
-        int idx = (krow + KSTEP * (code0 >> 1)) * W + lam + WS * (code0 & 1);
-        tie_merge<T>(best, idx, best1, (krow + KSTEP * (code1 >> 1) + WS) * W + lam + WS * (code1 & 1), eps);
-        for (int o = 32; o > 0; o >>= 1) {
-            const T ob = __shfl_xor(best, o);
-            const int oid = __shfl_xor(idx, o);
-            tie_merge<T>(best, idx, ob, oid, eps);
-        }
-        idx = __builtin_amdgcn_readfirstlane(idx);
+        // first maximum in sigma * W + rho order (within the tie band)
+        const int idx = select_lowest_max<T, WS, QPL>(m, eps, lane);
         u = idx / W;
         v = idx % W;
 
@@ -187,8 +174,8 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
             rr += Hr[o] * pr + Hi[o] * pi;
             ri += Hr[o] * pi - Hi[o] * pr;
         }
-        rr = __shfl(rr, owner);
-        ri = __shfl(ri, owner);
+        rr = readlane_f64(rr, owner);
+        ri = readlane_f64(ri, owner);
 
         // eqs. (15)-(16): delta = R_uv / D_uv, step gamma * delta; energy in FP64
         const double id = invD[idx];
