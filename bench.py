@@ -76,7 +76,7 @@ def kernel_hash(sources=None) -> str:
 def load_traffic(workload: str, sources=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "mixed_persistent_traffic.json")
+    path = os.path.join(ROOT, "profiles", "kernel_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -152,13 +152,14 @@ def run_dense(args, wl, cases):
     y = torch.from_numpy(c["y"]).to(dev)
     rows, cols = 2 * y.shape[0], 2 * y.shape[1]
     general = c.get("weights") is not None
+    pf = None
     if general:  # general layouts run on the dense form only
         pd = ljsde.plan_weights(c["weights"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA)
-        pf = None
     else:
         pd = ljsde.plan(c["tile"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA, fp64=True,
                         dense_c=True)
-        pf = ljsde.plan(c["tile"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA, fp64=True)
+        if not args.no_fp64:
+            pf = ljsde.plan(c["tile"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA, fp64=True)
     od = torch.empty((rows, cols), dtype=torch.float64, device=dev)
     of = torch.empty_like(od)
 
@@ -185,7 +186,16 @@ def run_dense(args, wl, cases):
         torch.cuda.synchronize()
         del a, b
 
-    # the first call builds the dense C of the image size (not timed)
+    # The first call builds the dense C of the image size (not timed). It also
+    # records the selections: the algorithmic HBM bytes are the distinct
+    # columns (class, frequency) the launch selects, each read once (windows of
+    # a class share their columns), plus the measurements and the output.
+    _, sel = ljsde.reconstruct_diag(y, pd, stream=stream)
+    torch.cuda.synchronize()
+    sel = sel.cpu().numpy().astype(np.int64)
+    _, cmap = ljsde.class_map(pd, y.shape[0], y.shape[1])
+    keys = cmap.astype(np.int64)[:, None] * (W * W) + sel
+    n_cols = int(np.unique(keys[sel >= 0]).size)
     msd = timed(lambda: ljsde.reconstruct(y, pd, out=od, stream=stream), args.steps, max(1, args.warmup))
     msf = None
     if pf is not None:
@@ -203,15 +213,6 @@ def run_dense(args, wl, cases):
         quality["oracle_sample_windows"] = len(oracle64_blocks)
     col_bytes = W * W * 16
     stream_bytes = nwin * iters * col_bytes  # one column of C per window-iteration (eq. (17))
-    # Algorithmic HBM bytes: every distinct column (class, frequency) the launch
-    # selects, read once (windows of a class share their columns), plus the
-    # measurements and the output.
-    _, sel = ljsde.reconstruct_diag(y, pd)
-    torch.cuda.synchronize()
-    sel = sel.cpu().numpy().astype(np.int64)
-    _, cmap = ljsde.class_map(pd, y.shape[0], y.shape[1])
-    keys = cmap.astype(np.int64)[:, None] * (W * W) + sel
-    n_cols = int(np.unique(keys[sel >= 0]).size)
     algo = n_cols * col_bytes + 8 * y.numel() + 8 * px
     achieved = algo / (msd * 1e-3) / 1e9
     rec = {

@@ -244,9 +244,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void de
 #pragma unroll
         for (int t = 0; t < QPL; ++t)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                R[t][c].re -= gr * cv[t][c].x - gi * cv[t][c].y;
-                R[t][c].im -= gr * cv[t][c].y + gi * cv[t][c].x;
+            for (int c = 0; c < 4; ++c) {  // two fused multiply-adds per component
+                R[t][c].re = fma(-gr, cv[t][c].x, fma(gi, cv[t][c].y, R[t][c].re));
+                R[t][c].im = fma(-gr, cv[t][c].y, fma(-gi, cv[t][c].x, R[t][c].im));
             }
     }
     if (j.sel != nullptr)

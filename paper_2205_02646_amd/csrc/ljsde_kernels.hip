@@ -113,10 +113,10 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
                 const int pos = ((kap - u) & (WS - 1)) * WS + ((lam - v) & (WS - 1));
                 const T *s = ldsS + pos * 2;
 #pragma unroll
-                for (int o = 0; o < 4; ++o) {
+                for (int o = 0; o < 4; ++o) {  // two fused multiply-adds per component
                     const T sr = s[o * NPOS * 2], si = s[o * NPOS * 2 + 1];
-                    P[t][o].re -= g4[o].re * sr - g4[o].im * si;
-                    P[t][o].im -= g4[o].re * si + g4[o].im * sr;
+                    P[t][o].re = fma(-g4[o].re, sr, fma(g4[o].im, si, P[t][o].re));
+                    P[t][o].im = fma(-g4[o].re, si, fma(-g4[o].im, sr, P[t][o].im));
                 }
             }
             // project: R(a, b) = sum_q (-1)^(qa a + qb b) e^{-i theta (qa k + qb l)} Q_q with the
