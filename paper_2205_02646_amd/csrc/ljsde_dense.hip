@@ -140,12 +140,12 @@ struct DenseLds {
 // (per-pixel quadrant weights: P_q of every quadrant, R = sum_q conj(e_q) P_q).
 template <int WS, int SHAPE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void dense_kernel(
-    KParams p, KJob j, const double2 *__restrict__ Cd) {
+    KParams p, KJob j, const double2 *__restrict__ Cd, const int *__restrict__ order) {
     extern __shared__ __align__(16) char lds[];
     constexpr int W = 2 * WS, NF = W * W, NPOS = WS * WS, QPL = NPOS / 64, KSTEP = 64 / WS;
-    const long long w = blockIdx.x;
-    const long long nwin = (long long)j.nbi * j.nbj;
-    if (w >= nwin) return;
+    const int wo = order[blockIdx.x];  // workgroup -> window (class-sorted, per-XCD chunks)
+    if (wo < 0) return;
+    const long long w = wo;
     const int bi = (int)(w / j.nbj), bj = (int)(w % j.nbj);
     const int lane = threadIdx.x & 63;
     const int lam = lane % WS, krow = lane / WS;
@@ -280,21 +280,24 @@ int launch_dense_c_build(const KParams &p, const unsigned char *tables, int n_cl
 }
 
 template <int WS, int SHAPE>
-static int launch_dense_t(const KParams &p, const KJob &job, const void *C, void *stream) {
-    const long long nwin = (long long)job.nbi * job.nbj;
-    if (nwin <= 0) return 0;
-    dense_kernel<WS, SHAPE><<<dim3((unsigned)nwin), dim3(64), DenseLds<WS>::bytes, (hipStream_t)stream>>>(
-        p, job, (const double2 *)C);
+static int launch_dense_t(const KParams &p, const KJob &job, const void *C, const int *order, int n,
+                          void *stream) {
+    if (n <= 0) return 0;
+    dense_kernel<WS, SHAPE><<<dim3((unsigned)n), dim3(64), DenseLds<WS>::bytes, (hipStream_t)stream>>>(
+        p, job, (const double2 *)C, order);
     return (int)hipGetLastError();
 }
 
-int launch_dense(const KParams &p, const KJob &job, const void *C, int ws, void *stream) {
+int launch_dense(const KParams &p, const KJob &job, const void *C, const int *order, int n, int ws, void *stream) {
     constexpr int TQ = SHAPE_THREE_QUARTER, QS = SHAPE_QUARTER, GN = SHAPE_GENERAL;
     if (p.shape == GN)
-        return ws == 16 ? launch_dense_t<16, GN>(p, job, C, stream) : launch_dense_t<8, GN>(p, job, C, stream);
+        return ws == 16 ? launch_dense_t<16, GN>(p, job, C, order, n, stream)
+                        : launch_dense_t<8, GN>(p, job, C, order, n, stream);
     if (p.shape == QS)
-        return ws == 16 ? launch_dense_t<16, QS>(p, job, C, stream) : launch_dense_t<8, QS>(p, job, C, stream);
-    return ws == 16 ? launch_dense_t<16, TQ>(p, job, C, stream) : launch_dense_t<8, TQ>(p, job, C, stream);
+        return ws == 16 ? launch_dense_t<16, QS>(p, job, C, order, n, stream)
+                        : launch_dense_t<8, QS>(p, job, C, order, n, stream);
+    return ws == 16 ? launch_dense_t<16, TQ>(p, job, C, order, n, stream)
+                    : launch_dense_t<8, TQ>(p, job, C, order, n, stream);
 }
 
 }  // namespace ljsde

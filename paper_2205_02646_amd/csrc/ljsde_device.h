@@ -368,22 +368,27 @@ __device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
 // index; eps = 0: the first maximum). Metrics are nonnegative. Uniform result.
 template <typename T, int WS, int QPL>
 __device__ __forceinline__ int select_lowest_max(const T m[][4], T eps, int lane) {
-    constexpr int W = 2 * WS, KSTEP = 64 / WS;
-    T lmax = T(0);
+    constexpr int W = 2 * WS, KSTEP = 64 / WS, N = 4 * QPL;
+    // reductions as trees: short dependency chains
+    T v[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = m[i >> 2][i & 3];
+#pragma unroll
+    for (int s = 1; s < N; s *= 2)
+#pragma unroll
+        for (int i = 0; i + s < N; i += 2 * s) v[i] = fmax(v[i], v[i + s]);
+    const T thr = wave_max_nonneg(v[0]) * (T(1) - eps);
+    // rank r = 8a + 2t + b orders this lane's indices (16: none reaches thr)
+    unsigned r[N];
 #pragma unroll
     for (int t = 0; t < QPL; ++t)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) lmax = fmax(lmax, m[t][c]);
-    const T thr = wave_max_nonneg(lmax) * (T(1) - eps);
-    // rank r = 8a + 2t + b orders this lane's indices
-    int rank = 16;
+        for (int c = 0; c < 4; ++c) r[4 * t + c] = m[t][c] >= thr ? (unsigned)(8 * (c >> 1) + 2 * t + (c & 1)) : 16u;
 #pragma unroll
-    for (int a = 1; a >= 0; --a)
+    for (int s = 1; s < N; s *= 2)
 #pragma unroll
-        for (int t = QPL - 1; t >= 0; --t)
-#pragma unroll
-            for (int b = 1; b >= 0; --b)
-                if (m[t][2 * a + b] >= thr) rank = 8 * a + 2 * t + b;
+        for (int i = 0; i + s < N; i += 2 * s) r[i] = min(r[i], r[i + s]);
+    const int rank = (int)r[0];
     const int ra = rank >> 3, rt = (rank >> 1) & 3, rb = rank & 1;
     const unsigned fidx = rank == 16 ? 0xFFFFFFFFu
                                      : (unsigned)((lane / WS + KSTEP * rt + WS * ra) * W + lane % WS + WS * rb);

@@ -89,6 +89,8 @@ struct SizeSet {
     int *d_rowcls = nullptr;
     int *d_colcls = nullptr;
     void *d_dense = nullptr;  // dense C of every class (LJSDE_DENSE_C plans), built on first use
+    int *d_order = nullptr;   // dense form: window of every workgroup (-1: none), see dense_order
+    int order_len = 0;
 };
 
 struct Plan {
@@ -1005,11 +1007,37 @@ int ljsde_set_energy_floor(int pattern_id, double tau) {
     return ok();
 }
 
+// Launch order of the dense form: windows sorted by class (row-major inside a
+// class) and cut into XCD_RANGES contiguous chunks of equal length; workgroup
+// b runs entry b / XCD_RANGES of chunk b % XCD_RANGES. Workgroups are dealt
+// to the XCDs round-robin, so each XCD works through a few classes at a time
+// and their hot columns of C stay in its L2.
+static std::vector<int> dense_order(const SizeSet &s) {
+    const int n = s.nbi * s.nbj, nck = (int)s.colkeys.size();
+    std::vector<int> win(n);
+    for (int i = 0; i < n; ++i) win[i] = i;
+    std::stable_sort(win.begin(), win.end(), [&](int a, int b) {
+        return s.rowcls[a / s.nbj] * nck + s.colcls[a % s.nbj] < s.rowcls[b / s.nbj] * nck + s.colcls[b % s.nbj];
+    });
+    const int cs = (n + XCD_RANGES - 1) / XCD_RANGES;
+    std::vector<int> order((size_t)cs * XCD_RANGES, -1);
+    for (int x = 0; x < XCD_RANGES; ++x)
+        for (int i = 0; i < cs && x * cs + i < n; ++i) order[(size_t)i * XCD_RANGES + x] = win[x * cs + i];
+    return order;
+}
+
 // Dense C of every class of a size set (eq. (14), FP64), built on the device
 // from the class tables on first use; refused with LJSDE_ENOMEM when it would
 // not fit in the free device memory with 1 GiB to spare.
 static int ensure_dense(Plan &p, SizeSet &s, void *stream) {
     if (s.d_dense) return LJSDE_OK;
+    if (!s.d_order) {
+        const std::vector<int> order = dense_order(s);
+        int st = dev_alloc((void **)&s.d_order, order.size() * sizeof(int));
+        if (st) return st;
+        HIP_TRY(hipMemcpy(s.d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice));
+        s.order_len = (int)order.size();
+    }
     const size_t bytes = dense_c_bytes(p.Ws, s.n_classes());
     size_t free_b = 0, total_b = 0;
     HIP_TRY(hipMemGetInfo(&free_b, &total_b));
@@ -1040,7 +1068,7 @@ static int reconstruct_impl(const void *y, int Ms, int Ns, int id, void *out, in
     if (p->flags & LJSDE_DENSE_C) {
         st = ensure_dense(*p, *s, stream);
         if (st) return st;
-        e = launch_dense(k, j, s->d_dense, p->Ws, stream);
+        e = launch_dense(k, j, s->d_dense, s->d_order, s->order_len, p->Ws, stream);
     } else if (p->fp64()) {
         e = launch_plain_f64(k, j, p->Ws, stream);
     } else if (sel) {
@@ -1159,6 +1187,7 @@ int ljsde_release(int pattern_id) {
         if (s.d_rowcls) (void)hipFree(s.d_rowcls);
         if (s.d_colcls) (void)hipFree(s.d_colcls);
         if (s.d_dense) (void)hipFree(s.d_dense);
+        if (s.d_order) (void)hipFree(s.d_order);
     }
     if (p->d_consts) (void)hipFree(p->d_consts);
     g_plans[pattern_id].reset();

@@ -90,7 +90,9 @@ int mixed_blocks_per_cu(int ws, int nw, int *blocks);
 size_t dense_c_bytes(int ws, int n_classes);
 int launch_dense_c_build(const KParams &p, const unsigned char *tables, int n_classes, int ws, void *out,
                          void *stream);
-int launch_dense(const KParams &p, const KJob &job, const void *C, int ws, void *stream);
+// order: window index per workgroup (-1: idle), order_len entries.
+int launch_dense(const KParams &p, const KJob &job, const void *C, const int *order, int order_len, int ws,
+                 void *stream);
 size_t mixed_lds_bytes(int ws, int nw);
 
 }  // namespace ljsde
