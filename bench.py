@@ -406,7 +406,15 @@ def main():
         "hbm_algorithmic_gbps": hbm_bytes / (ms32 * 1e-3) / 1e9,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
-                     "traffic": load_traffic(args.workload), "kernel_hash": kernel_hash()},
+                     "traffic": load_traffic(args.workload), "kernel_hash": kernel_hash(),
+                     "algorithmic_flops_per_launch": flops,
+                     "peak_unpacked": PEAK_FP32_VALU / 2e12,
+                     "frac_of_peak_unpacked": 2 * achieved / PEAK_FP32_VALU,
+                     "note": "algorithmic flops: 30 per frequency and iteration (projection 18, metric 4, "
+                             "update 8) x W^2 x iterations x windows. peak: the published FP32 vector "
+                             "peak, which counts packed FP32; this code is built with packed FP32 "
+                             "disabled, so its FP32 and FP64 instructions peak at half of it "
+                             "(peak_unpacked)"},
         "cpu_baseline": oracle_rec,
     }
     print(json.dumps(rec), flush=True)

@@ -408,3 +408,21 @@ def test_two_and_four_quadrant_masks_run_as_weights_plans(mask):
         _, _, Dref = O.rljsde_precompute(a, O.spatial_weights(W, 0.7) * valid.reshape(-1))
         np.testing.assert_allclose(D, Dref, rtol=0, atol=1e-12 * Dref.max())
     ljsde.release(pid)
+
+
+@pytest.mark.parametrize("kind", ["fp64", "weights", "half_pixels"])
+def test_batch_refuses_plans_without_a_batched_kernel(kind):
+    """Batched launches run the FP32 persistent kernel: FP64 plans, general
+    layouts and half/full pixels (dense FP64 form) are refused on the host."""
+    if kind == "fp64":
+        pid = ljsde.plan(TILE, iters=10, fp64=True)
+    elif kind == "weights":
+        pid = ljsde.plan_weights(WTILE, iters=10)
+    else:
+        pid = ljsde.plan(TILE, iters=10, fp64=True, dense_c=True, shape=0x3)
+    buf = (ctypes.c_double * 64)()
+    addr = ctypes.cast(buf, ctypes.c_void_p).value
+    jobs = (ljsde.Job * 1)(ljsde.Job(addr, 4, 4, pid, addr))
+    st = ljsde.lib().ljsde_reconstruct_batch(jobs, 1, None)
+    assert st == ljsde.EUNSUPPORTED and "FP32" in ljsde.last_error()
+    ljsde.release(pid)
