@@ -844,7 +844,7 @@ using namespace ljsde;
 
 extern "C" {
 
-int ljsde_version(void) { return 10000; }
+int ljsde_version(void) { return 10100; }  // 1.1: ljsde_plan_weights, LJSDE_WEIGHTS, every pixel-shape mask
 
 int ljsde_plan_info(int pattern_id, int *window, int *block, int *iters, unsigned *flags) {
     std::lock_guard<std::mutex> lk(g_mu);
