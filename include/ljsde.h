@@ -61,13 +61,16 @@ enum {
     LJSDE_STATE_FP32 = 16,    /* FP32 plans: keep the loop state and its updates in FP32 too
                                  (no FP64 re-decision); greedy selections can then diverge
                                  from FP64 at near ties */
-    LJSDE_DENSE_C = 32,       /* FP64 plans: the dense form of Sec. IV. Per class the full
+    LJSDE_DENSE_C = 32,       /* the dense form of Sec. IV, FP64 arithmetic. Per class the full
                                  W^2 x W^2 matrix C of eq. (14) is built in device memory
                                  (16 MiB per class at W = 32, on the first reconstruction of an
                                  image size; LJSDE_ENOMEM if it does not fit), each window
                                  keeps R of eq. (12) for all W^2 frequencies and subtracts a
                                  column of C per iteration (eq. (17)). Same results as the
-                                 factorised FP64 path; single-image calls only */
+                                 factorised FP64 path; single-image calls only. With
+                                 LJSDE_FP32 the measurements and the output are float (the
+                                 arithmetic stays FP64); not with LJSDE_DFT_SPLITBF16 or
+                                 LJSDE_STATE_FP32 */
     LJSDE_WEIGHTS = 64        /* reported by ljsde_plan_info for plans made by
                                  ljsde_plan_weights (ignored there, refused by ljsde_plan) */
 };
@@ -84,7 +87,7 @@ enum {
  * tables then report the relabelled codes). Masks with two bits (half and
  * diagonal pixels) or four (full pixels) run as their 0/1 quadrant weights on
  * the general-layout dense form (see ljsde_plan_weights): they need
- * LJSDE_FP64 | LJSDE_DENSE_C, else LJSDE_EUNSUPPORTED, and ljsde_plan_info
+ * LJSDE_DENSE_C, else LJSDE_EUNSUPPORTED, and ljsde_plan_info
  * reports LJSDE_WEIGHTS for them. LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32
  * exist for three-quarter sampling only.
  * Frequencies that no measurement of a window responds to (D of eq. (13) at
@@ -133,8 +136,9 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols,
  *            caller keeps ownership). 0/1 weights of a pixel shape give that
  *            shape's measurement matrix.
  *  window, block, iters, rho, gamma  as for ljsde_plan.
- *  flags     LJSDE_FP64 | LJSDE_DENSE_C, optionally LJSDE_Q_ONES; no pixel
- *            shape. Other precisions or the factorised form ->
+ *  flags     LJSDE_DENSE_C with LJSDE_FP64 (double measurements and output)
+ *            or LJSDE_FP32 (float; FP64 arithmetic either way), optionally
+ *            LJSDE_Q_ONES; no pixel shape. Without LJSDE_DENSE_C ->
  *            LJSDE_EUNSUPPORTED.
  * Per class the tables hold the ten spectra S_qq' = DFT(w A_q A_q') (q <= q')
  * and the per-pixel weights; C of eq. (14) is built from them on the device.

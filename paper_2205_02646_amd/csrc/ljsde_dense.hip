@@ -138,7 +138,9 @@ struct DenseLds {
 
 // One wavefront per window. SHAPE is a pixel-shape mask or SHAPE_GENERAL
 // (per-pixel quadrant weights: P_q of every quadrant, R = sum_q conj(e_q) P_q).
-template <int WS, int SHAPE>
+// IO is the element type of the measurements and the output (FP32 plans:
+// float; the arithmetic is FP64 either way).
+template <int WS, int SHAPE, typename IO>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void dense_kernel(
     KParams p, KJob j, const double2 *__restrict__ Cd, const int *__restrict__ order) {
     extern __shared__ __align__(16) char lds[];
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void de
     constexpr bool GENERAL = SHAPE == SHAPE_GENERAL;
     constexpr int PSHAPE = GENERAL ? SHAPE_QUARTER : SHAPE;  // Q_q = P_q
     const double *Aw = GENERAL ? (const double *)(tb + p.lay.offA) : nullptr;
-    const double e0 = window_prologue<double, WS, GENERAL>(p, j, bi, bj, codes, ldsX, ldsC, ldsS, P, Aw);
+    const double e0 = window_prologue<double, WS, GENERAL, IO>(p, j, bi, bj, codes, ldsX, ldsC, ldsS, P, Aw);
 
     // R(0) of eq. (12) through the factorised projection, and q / D
     const double *ew = p.c.ew;
@@ -252,9 +254,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void de
     if (j.sel != nullptr)
         for (int nu = nu_done + lane; nu < p.iters; nu += 64) j.sel[w * p.iters + nu] = -1;
     if (lane < BB) {
-        double *O = (double *)j.out;
+        IO *O = (IO *)j.out;
         const size_t row = (size_t)(p.B * bi + oi);
-        O[row * (size_t)(2 * j.Ns) + (size_t)(p.B * bj + oj)] = outacc;
+        O[row * (size_t)(2 * j.Ns) + (size_t)(p.B * bj + oj)] = (IO)outacc;
     }
 }
 
@@ -279,25 +281,33 @@ int launch_dense_c_build(const KParams &p, const unsigned char *tables, int n_cl
     return (int)hipGetLastError();
 }
 
-template <int WS, int SHAPE>
+template <int WS, int SHAPE, typename IO>
 static int launch_dense_t(const KParams &p, const KJob &job, const void *C, const int *order, int n,
                           void *stream) {
     if (n <= 0) return 0;
-    dense_kernel<WS, SHAPE><<<dim3((unsigned)n), dim3(64), DenseLds<WS>::bytes, (hipStream_t)stream>>>(
+    dense_kernel<WS, SHAPE, IO><<<dim3((unsigned)n), dim3(64), DenseLds<WS>::bytes, (hipStream_t)stream>>>(
         p, job, (const double2 *)C, order);
     return (int)hipGetLastError();
 }
 
-int launch_dense(const KParams &p, const KJob &job, const void *C, const int *order, int n, int ws, void *stream) {
+template <typename IO>
+static int launch_dense_io(const KParams &p, const KJob &job, const void *C, const int *order, int n, int ws,
+                           void *stream) {
     constexpr int TQ = SHAPE_THREE_QUARTER, QS = SHAPE_QUARTER, GN = SHAPE_GENERAL;
     if (p.shape == GN)
-        return ws == 16 ? launch_dense_t<16, GN>(p, job, C, order, n, stream)
-                        : launch_dense_t<8, GN>(p, job, C, order, n, stream);
+        return ws == 16 ? launch_dense_t<16, GN, IO>(p, job, C, order, n, stream)
+                        : launch_dense_t<8, GN, IO>(p, job, C, order, n, stream);
     if (p.shape == QS)
-        return ws == 16 ? launch_dense_t<16, QS>(p, job, C, order, n, stream)
-                        : launch_dense_t<8, QS>(p, job, C, order, n, stream);
-    return ws == 16 ? launch_dense_t<16, TQ>(p, job, C, order, n, stream)
-                    : launch_dense_t<8, TQ>(p, job, C, order, n, stream);
+        return ws == 16 ? launch_dense_t<16, QS, IO>(p, job, C, order, n, stream)
+                        : launch_dense_t<8, QS, IO>(p, job, C, order, n, stream);
+    return ws == 16 ? launch_dense_t<16, TQ, IO>(p, job, C, order, n, stream)
+                    : launch_dense_t<8, TQ, IO>(p, job, C, order, n, stream);
+}
+
+int launch_dense(const KParams &p, const KJob &job, const void *C, const int *order, int n, int ws, bool f32io,
+                 void *stream) {
+    return f32io ? launch_dense_io<float>(p, job, C, order, n, ws, stream)
+                 : launch_dense_io<double>(p, job, C, order, n, ws, stream);
 }
 
 }  // namespace ljsde

@@ -714,6 +714,8 @@ int prepare_batch(const ljsde_job *jobs, int n, void *stream, BatchState **out) 
         st = get_plan(jobs[i].pattern_id, &p);
         if (st) return st;
         if (p->fp64()) return fail(LJSDE_EUNSUPPORTED, "job %d: batched launches need FP32 plans", i);
+        if (p->flags & LJSDE_DENSE_C)
+            return fail(LJSDE_EUNSUPPORTED, "job %d: batched launches need FP32 plans of the factorised form", i);
         if (p->W != p0->W || p->B != p0->B || p->iters != p0->iters || p->gamma != p0->gamma ||
             p->tau != p0->tau || ((p->flags & LJSDE_STATE_FP32) != 0) != sf32 || p->shape != p0->shape ||
             ((p->flags ^ p0->flags) & LJSDE_DFT_SPLITBF16))
@@ -908,8 +910,8 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, i
         return fail(LJSDE_EINVAL, "exactly one of LJSDE_FP64 / LJSDE_FP32 is required");
     if ((flags & (LJSDE_DFT_SPLITBF16 | LJSDE_STATE_FP32)) && (flags & LJSDE_FP64))
         return fail(LJSDE_EINVAL, "LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32 apply to FP32 plans only");
-    if ((flags & LJSDE_DENSE_C) && !(flags & LJSDE_FP64))
-        return fail(LJSDE_EINVAL, "LJSDE_DENSE_C applies to FP64 plans only");
+    if ((flags & LJSDE_DENSE_C) && (flags & (LJSDE_DFT_SPLITBF16 | LJSDE_STATE_FP32)))
+        return fail(LJSDE_EINVAL, "LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32 do not apply to the dense form");
     if (!(window == 32 || window == 16))
         return fail(LJSDE_EUNSUPPORTED, "no kernel for window %d (have 16, 32)", window);
     if ((flags & LJSDE_DFT_SPLITBF16) && ((flags & LJSDE_STATE_FP32) || window != 32))
@@ -938,9 +940,9 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, i
     } else {
         // Two or four collected quadrants (half, diagonal and full pixels):
         // their 0/1 quadrant weights through the general-layout dense form.
-        if ((flags & (LJSDE_FP64 | LJSDE_DENSE_C)) != (LJSDE_FP64 | LJSDE_DENSE_C))
-            return fail(LJSDE_EUNSUPPORTED,
-                        "pixel shape mask 0x%x runs on the dense FP64 form only (LJSDE_FP64 | LJSDE_DENSE_C)", mask);
+        if (!(flags & LJSDE_DENSE_C))
+            return fail(LJSDE_EUNSUPPORTED, "pixel shape mask 0x%x runs on the dense form only (LJSDE_DENSE_C)",
+                        mask);
         p->quad.resize(n * 4);
         for (size_t i = 0; i < n; ++i)
             for (int q = 0; q < 4; ++q) p->quad[i * 4 + q] = (double)((mask >> (q ^ pattern[i])) & 1);
@@ -973,15 +975,15 @@ int ljsde_plan_weights(const double *weights, int pat_rows, int pat_cols, int wi
         return fail(LJSDE_EINVAL, "exactly one of LJSDE_FP64 / LJSDE_FP32 is required");
     if ((flags & (LJSDE_DFT_SPLITBF16 | LJSDE_STATE_FP32)) && (flags & LJSDE_FP64))
         return fail(LJSDE_EINVAL, "LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32 apply to FP32 plans only");
-    if ((flags & LJSDE_DENSE_C) && !(flags & LJSDE_FP64))
-        return fail(LJSDE_EINVAL, "LJSDE_DENSE_C applies to FP64 plans only");
+    if ((flags & LJSDE_DENSE_C) && (flags & (LJSDE_DFT_SPLITBF16 | LJSDE_STATE_FP32)))
+        return fail(LJSDE_EINVAL, "LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32 do not apply to the dense form");
     if (!(window == 32 || window == 16))
         return fail(LJSDE_EUNSUPPORTED, "no kernel for window %d (have 16, 32)", window);
     if (!(block == 4 || block == 8))
         return fail(LJSDE_EUNSUPPORTED, "no kernel for block %d (have 4, 8)", block);
     if (iters > 32767) return fail(LJSDE_EUNSUPPORTED, "iters %d above 32767", iters);
-    if ((flags & (LJSDE_FP64 | LJSDE_DENSE_C)) != (LJSDE_FP64 | LJSDE_DENSE_C))
-        return fail(LJSDE_EUNSUPPORTED, "general layouts run on the dense FP64 form only (LJSDE_FP64 | LJSDE_DENSE_C)");
+    if (!(flags & LJSDE_DENSE_C))
+        return fail(LJSDE_EUNSUPPORTED, "general layouts run on the dense form only (LJSDE_DENSE_C)");
     auto p = std::make_unique<Plan>();
     p->quad.assign(weights, weights + n);
     p->pattern.assign((size_t)pat_rows * pat_cols, 0);
@@ -1068,7 +1070,7 @@ static int reconstruct_impl(const void *y, int Ms, int Ns, int id, void *out, in
     if (p->flags & LJSDE_DENSE_C) {
         st = ensure_dense(*p, *s, stream);
         if (st) return st;
-        e = launch_dense(k, j, s->d_dense, s->d_order, s->order_len, p->Ws, stream);
+        e = launch_dense(k, j, s->d_dense, s->d_order, s->order_len, p->Ws, !p->fp64(), stream);
     } else if (p->fp64()) {
         e = launch_plain_f64(k, j, p->Ws, stream);
     } else if (sel) {

@@ -91,8 +91,9 @@ size_t dense_c_bytes(int ws, int n_classes);
 int launch_dense_c_build(const KParams &p, const unsigned char *tables, int n_classes, int ws, void *out,
                          void *stream);
 // order: window index per workgroup (-1: idle), order_len entries.
+// f32io: float measurements and output (FP32 plans), else double.
 int launch_dense(const KParams &p, const KJob &job, const void *C, const int *order, int order_len, int ws,
-                 void *stream);
+                 bool f32io, void *stream);
 size_t mixed_lds_bytes(int ws, int nw);
 
 }  // namespace ljsde

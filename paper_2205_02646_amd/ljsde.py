@@ -109,8 +109,8 @@ def plan(pattern, window: int = 32, block: int = 4, iters: int = 100, rho: float
     """Register a plan for a pattern tile of quadrant codes; returns its id.
     ``shape`` is the pixel-shape mask (0 or SHAPE_THREE_QUARTER: L-shaped
     pixels; SHAPE_QUARTER: one transparent quadrant per pixel). ``dense_c``
-    (FP64 plans) selects the dense form: per class the full C of eq. (14) in
-    device memory, R as the loop state."""
+    selects the dense form (FP64 arithmetic; float32 I/O for FP32 plans): per
+    class the full C of eq. (14) in device memory, R as the loop state."""
     pat = np.ascontiguousarray(np.asarray(pattern, dtype=np.uint8))
     if pat.ndim != 2:
         raise ValueError("pattern must be 2-D")
@@ -121,14 +121,15 @@ def plan(pattern, window: int = 32, block: int = 4, iters: int = 100, rho: float
 
 
 def plan_weights(weights, window: int = 32, block: int = 4, iters: int = 100, rho: float = 0.7,
-                 gamma: float = 0.5, q_ones: bool = False) -> int:
+                 gamma: float = 0.5, q_ones: bool = False, fp64: bool = True) -> int:
     """Register a plan for a general layout: ``weights`` is a [rows, cols, 4]
     tile of per-pixel quadrant weights (quadrant 2a + b of the footprint).
-    Runs on the dense FP64 form."""
+    Runs on the dense form in FP64; ``fp64=False`` takes float32
+    measurements and returns float32 images."""
     wt = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
     if wt.ndim != 3 or wt.shape[2] != 4:
         raise ValueError("weights must be a [rows, cols, 4] tile")
-    flags = FP64 | DENSE_C | (Q_ONES if q_ones else 0)
+    flags = (FP64 if fp64 else FP32) | DENSE_C | (Q_ONES if q_ones else 0)
     return _check(lib().ljsde_plan_weights(wt.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), wt.shape[0],
                                            wt.shape[1], window, block, iters, rho, gamma, flags))
 

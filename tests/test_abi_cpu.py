@@ -55,10 +55,12 @@ TILE = random_pattern(4, 4, seed=0)
     (dict(fp64=True, state_fp32=True), ljsde.EINVAL),
     (dict(splitbf16=True, state_fp32=True), ljsde.EUNSUPPORTED),
     (dict(splitbf16=True, window=16), ljsde.EUNSUPPORTED),
-    (dict(dense_c=True), ljsde.EINVAL),          # the dense form exists for FP64 plans
+    (dict(dense_c=True, splitbf16=True), ljsde.EINVAL),   # options of the factorised FP32 kernel
+    (dict(dense_c=True, state_fp32=True), ljsde.EINVAL),
     (dict(shape=0x3), ljsde.EUNSUPPORTED),      # half pixels: dense FP64 form only
     (dict(shape=0xF), ljsde.EUNSUPPORTED),
     (dict(shape=0x6, fp64=True), ljsde.EUNSUPPORTED),
+    (dict(shape=0x6), ljsde.EUNSUPPORTED),
     (dict(shape=0x4, splitbf16=True), ljsde.EUNSUPPORTED),   # a relabelled quarter sampling
     (dict(shape=ljsde.SHAPE_QUARTER, splitbf16=True), ljsde.EUNSUPPORTED),
     (dict(shape=ljsde.SHAPE_QUARTER, state_fp32=True), ljsde.EUNSUPPORTED),
@@ -272,7 +274,7 @@ WTILE = random_weights(3, 4, seed=5)
     (dict(iters=0), None, ljsde.EINVAL),
     (dict(gamma=2.0), None, ljsde.EINVAL),
     (dict(window=64), None, ljsde.EUNSUPPORTED),
-    (dict(), ljsde.FP32, ljsde.EUNSUPPORTED),                       # dense FP64 form only
+    (dict(), ljsde.FP32, ljsde.EUNSUPPORTED),                       # dense form only
     (dict(), ljsde.FP64, ljsde.EUNSUPPORTED),                       # not the factorised form
     (dict(), ljsde.FP64 | ljsde.DENSE_C | ljsde.SHAPE(0x1), ljsde.EINVAL),  # no pixel shape
     (dict(), ljsde.FP64 | ljsde.FP32 | ljsde.DENSE_C, ljsde.EINVAL),
@@ -426,3 +428,19 @@ def test_batch_refuses_plans_without_a_batched_kernel(kind):
     st = ljsde.lib().ljsde_reconstruct_batch(jobs, 1, None)
     assert st == ljsde.EUNSUPPORTED and "FP32" in ljsde.last_error()
     ljsde.release(pid)
+
+
+def test_fp32_dense_plans_are_accepted_and_not_batched():
+    """FP32 plans of the dense form (float I/O, FP64 arithmetic), for codes,
+    half pixels and general layouts; batched launches refuse them."""
+    pids = [ljsde.plan(TILE, iters=10, dense_c=True), ljsde.plan(TILE, iters=10, dense_c=True, shape=0x3),
+            ljsde.plan_weights(WTILE, iters=10, fp64=False)]
+    for pid in pids:
+        f = ljsde.plan_info(pid)["flags"]
+        assert f & ljsde.FP32 and f & ljsde.DENSE_C
+        buf = (ctypes.c_float * 64)()
+        addr = ctypes.cast(buf, ctypes.c_void_p).value
+        jobs = (ljsde.Job * 1)(ljsde.Job(addr, 4, 4, pid, addr))
+        assert ljsde.lib().ljsde_reconstruct_batch(jobs, 1, None) == ljsde.EUNSUPPORTED
+        assert "factorised" in ljsde.last_error()
+        ljsde.release(pid)

@@ -193,3 +193,32 @@ def test_every_pixel_shape_matches_oracle(L, name):
     else:
         with pytest.raises(L.LjsdeError):
             L.plan(c["tile"], **kw)
+
+
+@pytest.mark.parametrize("kind,name", [("weights", "random_w32b4_ragged"), ("weights", "random_w16b8"),
+                                       ("mask", "half3_w32b4"), ("mask", "full_w32b4"), ("mask", "mask7_w32b4"),
+                                       ("mask", "mask4_w32b4")])
+def test_fp32_dense_plans_match_oracle_on_float32_input(L, kind, name):
+    """FP32 plans of the dense form: float32 measurements and output, FP64
+    arithmetic. Against the oracle run on the same float32 measurements the
+    selections are equal and the output differs by its float32 rounding."""
+    if kind == "weights":
+        rows, cols, per, wkind, W, B, iters, rho, gamma, q_ones, seed = WCASES[name]
+        pr, pc = (rows, cols) if per is None else per
+        wt = _tile(wkind, pr, pc, seed)
+        _, f = synthetic_image(2 * rows, 2 * cols, seed=seed)
+        y32 = sense_weights(f, wt).astype(np.float32)
+        ref, tr = O.reconstruct(y32.astype(np.float64), None, traces=True, weights=wt, W=W, B=B, iters=iters,
+                                rho=rho, gamma=gamma, form="RL", q_mode="ones" if q_ones else "fsr")
+        pid = L.plan_weights(wt, window=W, block=B, iters=iters, rho=rho, gamma=gamma, q_ones=q_ones, fp64=False)
+    else:
+        rows, cols, per, W, B, iters, seed, mask = MASK_CASES[name]
+        c = make_case(rows, cols, per, seed=seed, shape=mask)
+        y32 = c["y"].astype(np.float32)
+        ref, tr = O.reconstruct(y32.astype(np.float64), c["tile"], traces=True, W=W, B=B, iters=iters, form="RL",
+                                shape=mask)
+        pid = L.plan(c["tile"], window=W, block=B, iters=iters, shape=mask, dense_c=True)
+    out, sel = L.reconstruct_diag(_dev(y32, np.float32), pid)
+    assert out.dtype == torch.float32
+    _check(out, sel, ref, tr, B, 1e-4, f"{name} FP32 dense")
+    L.release(pid)
