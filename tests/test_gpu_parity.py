@@ -184,22 +184,35 @@ def test_constant_image_closed_form_on_gpu(L):
         L.release(pid)
 
 
-def test_energy_floor_stops_early_like_a_shorter_oracle_run(L):
+@pytest.mark.parametrize("form", ["fp64", "fp64_dense", "fp32", "fp32_dense"])
+def test_energy_floor_stops_early_like_a_shorter_oracle_run(L, form):
+    """The optional energy floor: a window stops after the first iteration
+    whose weighted residual energy (eq. (8), from the oracle's L-JSDE
+    residual) is at most tau times its initial value, and its output is that
+    of the shorter oracle run."""
+    tau = 0.02
     c = make_case(40, 40, 4, seed=31)
-    pid = L.plan(c["tile"], iters=60, fp64=True)
-    L.set_energy_floor(pid, 0.02)
-    out, sel = L.reconstruct_diag(_dev(c["y"], np.float64), pid)
-    out = out.cpu().numpy()
+    fp64 = form.startswith("fp64")
+    y = c["y"] if fp64 else c["y"].astype(np.float32).astype(np.float64)
+    pid = L.plan(c["tile"], iters=60, fp64=fp64, dense_c=form.endswith("dense"))
+    L.set_energy_floor(pid, tau)
+    out, sel = L.reconstruct_diag(_dev(y, np.float64 if fp64 else np.float32), pid)
+    out = out.cpu().numpy().astype(np.float64)
     sel = sel.cpu().numpy()
     n_done = (sel >= 0).sum(axis=1)
     assert n_done.min() < 60                        # some windows stopped
     assert all((sel[w, n:] == -1).all() for w, n in enumerate(n_done))
     nbj = 40 // 4
+    tol = FP64_TOL if form == "fp64" or form == "fp64_dense" else 1e-4
     for w in range(sel.shape[0]):
         bi, bj = divmod(w, nbj)
-        ref = O.reconstruct(c["y"], c["tile"], iters=int(n_done[w]), form="RL", blocks=[(bi, bj)])
+        _, trL = O.reconstruct(y, c["tile"], iters=60, form="L", blocks=[(bi, bj)], traces=True)
+        t = trL[(bi, bj)]
+        stop = next((k + 1 for k, e in enumerate(t.energy) if e <= tau * t.energy0), 60)
+        assert n_done[w] == stop, (w, n_done[w], stop)
+        ref = O.reconstruct(y, c["tile"], iters=int(n_done[w]), form="RL", blocks=[(bi, bj)])
         blk = np.s_[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4]
-        assert np.max(np.abs(out[blk] - ref[blk])) <= FP64_TOL
+        assert np.max(np.abs(out[blk] - ref[blk])) <= tol
     L.release(pid)
 
 
