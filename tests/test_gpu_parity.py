@@ -184,6 +184,32 @@ def test_constant_image_closed_form_on_gpu(L):
         L.release(pid)
 
 
+@pytest.mark.parametrize("form", ["fp64", "fp64_dense", "fp32", "fp32_dense", "fp32_batched"])
+def test_zero_measurements_give_a_zero_image_and_dc_picks(L, form):
+    """y = 0: every metric of eq. (11) is 0, so every pick is the lowest index
+    (DC, by the tie rule), every step is 0 and the image is 0; the oracle
+    agrees. With an energy floor the window stops after its first pick."""
+    tile = random_pattern(4, 4, seed=9)
+    y = np.zeros((20, 24))
+    ref, tr = O.reconstruct(y, tile, W=32, B=4, iters=10, form="RL", traces=True)
+    assert all(t.picks == [0] * 10 for t in tr.values()) and not ref.any()
+    fp64 = form.startswith("fp64")
+    dt = np.float64 if fp64 else np.float32
+    pid = L.plan(tile, iters=10, fp64=fp64, dense_c=form.endswith("dense"))
+    if form == "fp32_batched":
+        out = L.reconstruct(_dev(y, dt), pid)
+        assert not out.cpu().numpy().any()
+    else:
+        out, sel = L.reconstruct_diag(_dev(y, dt), pid)
+        assert not out.cpu().numpy().any()
+        assert (sel.cpu().numpy() == 0).all()
+        L.set_energy_floor(pid, 0.5)
+        out, sel = L.reconstruct_diag(_dev(y, dt), pid)
+        sel = sel.cpu().numpy()
+        assert (sel[:, 0] == 0).all() and (sel[:, 1:] == -1).all()
+    L.release(pid)
+
+
 @pytest.mark.parametrize("form", ["fp64", "fp64_dense", "fp32", "fp32_dense"])
 def test_energy_floor_stops_early_like_a_shorter_oracle_run(L, form):
     """The optional energy floor: a window stops after the first iteration
