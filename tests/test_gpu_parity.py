@@ -264,3 +264,33 @@ def test_splitbf16_dft_accuracy_after_one_iteration(L):
     print(f"split-BF16, 1 iteration: {len(same)}/{sel.shape[0]} equal picks, max-abs {err:.3e} (scale {scale:.1f})")
     assert err <= 2e-4 * scale
     L.release(pid)
+
+
+def test_autotune_keeps_results_and_writes_its_cache(L, tmp_path, monkeypatch):
+    """Every launch variant the autotuner times computes each window the same
+    way: the batch gives bitwise the same images before and after tuning, and
+    the choice is written to the file named by LJSDE_TUNE_CACHE."""
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("LJSDE_TUNE_CACHE", str(cache))
+    items = []
+    for k, (r, cc, per) in enumerate([(40, 56, 2), (64, 48, 4), (24, 32, 8)]):
+        case = make_case(r, cc, per, seed=60 + k)
+        pid = L.plan(case["tile"], iters=25)
+        items.append((_dev(case["y"].astype(np.float32), np.float32), pid,
+                      torch.empty((r, cc), dtype=torch.float32, device="cuda:0")))
+    L.reconstruct_batch(items)
+    before = [o.clone() for _, _, o in items]
+    L.autotune(items)
+    for _, _, o in items:
+        o.zero_()
+    L.reconstruct_batch(items)
+    torch.cuda.synchronize()
+    for b, (_, _, o) in zip(before, items):
+        assert torch.equal(b, o)
+    import json
+    tuned = json.loads(cache.read_text())
+    assert len(tuned) >= 1
+    for v in tuned.values():
+        assert len(v) == 3 and v[0] in (1, 2, 4) and v[2] in (0, 1)
+    for _, pid, _ in items:
+        L.release(pid)
