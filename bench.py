@@ -23,6 +23,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -65,11 +66,19 @@ DENSE_KERNEL_SOURCES = ["paper_2205_02646_amd/csrc/ljsde_dense.hip", "paper_2205
                         "paper_2205_02646_amd/csrc/ljsde_device.h", "paper_2205_02646_amd/csrc/ljsde_internal.h"]
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and blank space, so that the hash follows
+    the code the counters were taken on, not its comments."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_hash(sources=None) -> str:
     h = hashlib.sha256()
     for f in (sources or KERNEL_SOURCES):
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

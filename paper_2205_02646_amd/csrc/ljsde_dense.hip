@@ -5,14 +5,15 @@
 // R(sigma, rho) of all W^2 frequencies as its state (eq. (12) at r = y); every
 // iteration selects by eq. (11), steps by eqs. (15)-(16) and subtracts
 // gamma * delta times column (u, v) of C (eq. (17)). Per window-iteration the
-// work is one metric per frequency and one complex multiply-add per
-// frequency, and the column read is W^2 * 16 bytes (16 KiB at W = 32): the
-// iteration is bound by the bandwidth of the cache level that holds C, not by
-// the VALU.
+// work is one metric per frequency, the selection and one complex
+// multiply-add per frequency, and the column read is W^2 * 16 bytes (16 KiB
+// at W = 32), which depends on the pick: the loop is bound by the VALU and
+// the latency of that read (columns are mostly served from L2).
 //
-// C is built on the device from the factorised class tables,
-// C(f, g) = sum_o conj(H_o(f)) H_o(g) S_o(f - g) (the same matrix as eq. (14),
-// see ljsde_kernels.hip), and stored so that a wavefront's read of one column
+// C is built on the device from the class tables: for pixel shapes from the
+// factorised form C(f, g) = sum_o conj(H_o(f)) H_o(g) S_o(f - g) (the same
+// matrix as eq. (14), see ljsde_kernels.hip), for general layouts from the
+// ten spectra S_qq'. It is stored so that a wavefront's read of one column
 // is 16 loads of 64 consecutive complex values.
 #include <hip/hip_runtime.h>
 

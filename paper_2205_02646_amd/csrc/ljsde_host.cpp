@@ -6,7 +6,9 @@
 // matrix and reuses them for every window with the same one. For
 // three-quarter sampling all of C factorises through four weighted-mask
 // spectra S_o (one per opaque-quadrant orientation), so a class costs a few
-// tens of KiB instead of the dense C of W^4 complex entries.
+// tens of KiB instead of the dense C of W^4 complex entries. General layouts
+// (per-pixel quadrant weights) keep ten spectra S_qq' per class and run on
+// the dense form, whose C is built on the device from them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
