@@ -108,6 +108,17 @@ def _oracle_worker(args):
     return [(bi, bj, out[B * bi:B * bi + B, B * bj:B * bj + B], tr[(bi, bj)].picks) for bi, bj in blocks]
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(y, tile, iters: int, n_windows: int, seed: int = 1, label: str = "", shape: int = 0xE,
                  weights=None):
     """Time the FP64 oracle (RL-JSDE form) on a random sample of windows over
@@ -126,10 +137,19 @@ def cpu_baseline(y, tile, iters: int, n_windows: int, seed: int = 1, label: str 
     dt = time.perf_counter() - t0
     res = {(bi, bj): blk for part in parts for bi, bj, blk, _ in part}
     picks = {(bi, bj): pk for part in parts for bi, bj, _, pk in part}
+    # one core on a part of the same sample, beside the paper's single-core rows
+    one = chunks[0]
+    t1 = time.perf_counter()
+    with mp.get_context("fork").Pool(1) as pool:
+        pool.map(_oracle_worker, [(y, tile, one, iters, shape, weights)])
+    dt1 = time.perf_counter() - t1
     rec = {"value": n_windows * B * B / dt / 1e6, "unit": "MP/s", "cores": cores, "kind": "oracle",
            "sample": f"{n_windows} random windows ({n_windows * B * B} px) of the {label}, RL-JSDE form "
                      f"(dense per-class B, C, D), {iters} iterations, {dt:.1f} s wall on {cores} processes "
                      f"with 1 BLAS thread each"}
+    rec["single_core"] = {"value": len(one) * B * B / dt1 / 1e6, "unit": "MP/s",
+                          "sample": f"{len(one)} of those windows on one process, {dt1:.1f} s"}
+    rec["cpu_model"] = _cpu_model()
     return rec, res, picks
 
 
