@@ -197,7 +197,7 @@ typedef struct {
  * pattern in one persistent launch, captured once as a HIP graph per batch
  * shape and replayed afterwards. All jobs must use FP32 plans with the same
  * window, block and iteration count. `jobs` is host memory, read during the
- * call only.
+ * call only; an empty batch is LJSDE_EINVAL.
  */
 int ljsde_reconstruct_batch(const ljsde_job *jobs, int n_jobs, void *stream);
 

@@ -444,3 +444,9 @@ def test_fp32_dense_plans_are_accepted_and_not_batched():
         assert ljsde.lib().ljsde_reconstruct_batch(jobs, 1, None) == ljsde.EUNSUPPORTED
         assert "factorised" in ljsde.last_error()
         ljsde.release(pid)
+
+
+def test_empty_batch_is_refused():
+    assert ljsde.lib().ljsde_reconstruct_batch(None, 0, None) == ljsde.EINVAL
+    assert ljsde.lib().ljsde_autotune(None, 0, None) == ljsde.EINVAL
+    assert "empty" in ljsde.last_error()
