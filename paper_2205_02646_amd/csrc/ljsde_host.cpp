@@ -732,7 +732,9 @@ int prepare_batch(const ljsde_job *jobs, int n, void *stream, BatchState **out) 
     int dev = 0;
     st = current_device(&dev);
     if (st) return st;
-    key << "@" << dev;
+    // one state per stream: launches on different streams may overlap, and
+    // each needs its own work counters and job table
+    key << "@" << dev << "/s" << (uintptr_t)stream;
     auto &slot = g_batches[key.str()];
     if (!slot) {
         auto b = std::make_unique<BatchState>();
@@ -1037,9 +1039,15 @@ static int ensure_dense(Plan &p, SizeSet &s, void *stream) {
     if (s.d_dense) return LJSDE_OK;
     if (!s.d_order) {
         const std::vector<int> order = dense_order(s);
-        int st = dev_alloc((void **)&s.d_order, order.size() * sizeof(int));
+        int *d = nullptr;
+        int st = dev_alloc((void **)&d, order.size() * sizeof(int));
         if (st) return st;
-        HIP_TRY(hipMemcpy(s.d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice));
+        const hipError_t e = hipMemcpy(d, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return fail(LJSDE_EHIP, "dense launch order upload: %s", hipGetErrorString(e));
+        }
+        s.d_order = d;
         s.order_len = (int)order.size();
     }
     const size_t bytes = dense_c_bytes(p.Ws, s.n_classes());
@@ -1048,10 +1056,17 @@ static int ensure_dense(Plan &p, SizeSet &s, void *stream) {
     if (bytes + (1ull << 30) > free_b)
         return fail(LJSDE_ENOMEM, "dense C needs %.1f GiB for %d classes, %.1f GiB free", bytes / 1073741824.0,
                     s.n_classes(), free_b / 1073741824.0);
-    int st = dev_alloc(&s.d_dense, bytes);
+    void *c = nullptr;
+    int st = dev_alloc(&c, bytes);
     if (st) return st;
-    const int e = launch_dense_c_build(make_params(p), s.d_tables, s.n_classes(), p.Ws, s.d_dense, stream);
-    if (e) return fail(LJSDE_EHIP, "dense C build: %s", hipGetErrorString((hipError_t)e));
+    int e = launch_dense_c_build(make_params(p), s.d_tables, s.n_classes(), p.Ws, c, stream);
+    // complete before it is published: then any call, on any stream, can read it
+    if (!e) e = (int)hipStreamSynchronize((hipStream_t)stream);
+    if (e) {
+        (void)hipFree(c);
+        return fail(LJSDE_EHIP, "dense C build: %s", hipGetErrorString((hipError_t)e));
+    }
+    s.d_dense = c;
     return LJSDE_OK;
 }
 

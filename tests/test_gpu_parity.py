@@ -294,3 +294,46 @@ def test_autotune_keeps_results_and_writes_its_cache(L, tmp_path, monkeypatch):
         assert len(v) == 3 and v[0] in (1, 2, 4) and v[2] in (0, 1)
     for _, pid, _ in items:
         L.release(pid)
+
+
+def test_calls_on_two_streams_may_overlap(L):
+    """The same batch launched on two streams without a wait in between (each
+    stream has its own work counters and job table), and a dense-form plan
+    whose first call builds C on one stream while the next call runs on
+    another: every image equals its single-stream result."""
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    items, refs = [], []
+    for k, (r, cc, per) in enumerate([(48, 64, 4), (32, 40, 2)]):
+        case = make_case(r, cc, per, seed=80 + k)
+        pid = L.plan(case["tile"], iters=40)
+        y = _dev(case["y"].astype(np.float32), np.float32)
+        items.append((y, pid))
+        refs.append(L.reconstruct(y, pid))
+    torch.cuda.synchronize()
+    outs = []
+    for st in (s1, s2):
+        jobs = [(y, pid, torch.empty((2 * y.shape[0], 2 * y.shape[1]), dtype=torch.float32, device="cuda:0"))
+                for y, pid in items]
+        L.reconstruct_batch(jobs, stream=st)
+        outs.append([o for _, _, o in jobs])
+    torch.cuda.synchronize()
+    for per_stream in outs:
+        for ref, o in zip(refs, per_stream):
+            assert torch.equal(ref, o)
+    for _, pid in items:
+        L.release(pid)
+    # dense form: C is complete before a call on another stream can read it
+    case = make_case(256, 256, 4, seed=83)
+    pid = L.plan(case["tile"], iters=30, fp64=True, dense_c=True)
+    y = _dev(case["y"], np.float64)
+    o1 = L.reconstruct(y, pid, stream=s1)
+    o2 = L.reconstruct(y, pid, stream=s2)
+    torch.cuda.synchronize()
+    assert torch.equal(o1, o2)
+    blocks = [(0, 0), (31, 17), (63, 63)]
+    ref = O.reconstruct(case["y"], case["tile"], iters=30, form="RL", blocks=blocks)
+    o = o2.cpu().numpy()
+    for bi, bj in blocks:
+        blk = np.s_[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4]
+        assert np.max(np.abs(o[blk] - ref[blk])) <= FP64_TOL
+    L.release(pid)
