@@ -195,9 +195,11 @@ typedef struct {
 /*
  * ljsde_reconstruct_batch -- reconstruct many images of uneven size and
  * pattern in one persistent launch, captured once as a HIP graph per batch
- * shape and replayed afterwards. All jobs must use FP32 plans with the same
- * window, block and iteration count. `jobs` is host memory, read during the
- * call only; an empty batch is LJSDE_EINVAL.
+ * shape and stream and replayed afterwards (device state per batch shape and
+ * stream, kept until a plan of the batch is released; launches on different
+ * streams may overlap). All jobs must use FP32 plans of the factorised form
+ * with the same window, block and iteration count. `jobs` is host memory,
+ * read during the call only; an empty batch is LJSDE_EINVAL.
  */
 int ljsde_reconstruct_batch(const ljsde_job *jobs, int n_jobs, void *stream);
 

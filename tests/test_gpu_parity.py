@@ -337,3 +337,24 @@ def test_calls_on_two_streams_may_overlap(L):
         blk = np.s_[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4]
         assert np.max(np.abs(o[blk] - ref[blk])) <= FP64_TOL
     L.release(pid)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp64_dense", "fp32_batched"])
+def test_failed_allocation_reports_enomem_and_leaves_no_partial_state(L, form, monkeypatch):
+    """A device allocation that fails (simulated: LJSDE_FAULT=alloc) is
+    reported as LJSDE_ENOMEM, and the next call, with memory available, builds
+    everything it needs and returns the right image."""
+    case = make_case(32, 40, 4, seed=90)
+    fp64 = form.startswith("fp64")
+    y = case["y"] if fp64 else case["y"].astype(np.float32).astype(np.float64)
+    pid = L.plan(case["tile"], iters=20, fp64=fp64, dense_c=form == "fp64_dense")
+    yd = _dev(y, np.float64 if fp64 else np.float32)
+    monkeypatch.setenv("LJSDE_FAULT", "alloc")
+    with pytest.raises(L.LjsdeError) as e:
+        L.reconstruct(yd, pid)
+    assert e.value.code == L.ENOMEM
+    monkeypatch.delenv("LJSDE_FAULT")
+    out = L.reconstruct(yd, pid).cpu().numpy().astype(np.float64)
+    ref = O.reconstruct(y, case["tile"], iters=20, form="RL")
+    assert np.max(np.abs(out - ref)) <= (FP64_TOL if fp64 else 0.05)
+    L.release(pid)
