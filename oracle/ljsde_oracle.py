@@ -59,7 +59,11 @@ in the design notes of the repository):
   FP64 its D is rounding noise, some 1e-32 of the largest D, and its metric
   would be noise divided by noise. Reading: a frequency whose D is at most
   D_REL = 1e-13 times the largest D of the same local measurement matrix is
-  unobserved and gets metric 0 (never selected); D <= 0 likewise.
+  unobserved and gets metric 0 (never selected); D <= 0 likewise. When every
+  metric is 0 the first index is the pick; if that frequency is unobserved
+  (a general layout whose weights vanish on the whole window leaves every D
+  at 0) its step is 0: nothing in the window constrains it, and the model
+  stays as it is.
 * Ties in the argmax of eqs. (10)/(11) are left open by the paper. They are
   exact, not rare: conjugate partners tie whenever the residual is real, and
   a sparse pattern can make two basis functions alias (their measurement
@@ -276,12 +280,22 @@ def _select(metric: np.ndarray):
     return k, gap
 
 
+def _observed(D):
+    # frequencies with a defined step: D > 0 and above D_REL of the largest D
+    return (D > 0) & (D > D_REL * D.max())
+
+
 def _metric(q, R, D):
-    # q |R|^2 / D of eqs. (10)/(11); unobserved frequencies (D <= D_REL max D) get 0
+    # q |R|^2 / D of eqs. (10)/(11); unobserved frequencies get 0
     out = np.zeros(D.shape)
-    pos = (D > 0) & (D > D_REL * D.max())
+    pos = _observed(D)
     out[pos] = q[pos] * np.abs(R[pos]) ** 2 / D[pos]
     return out
+
+
+def _step(R, D, obs, k):
+    # delta of eq. (16); an unobserved frequency takes no step
+    return R[k] / D[k] if obs[k] else 0.0
 
 
 def ljsde_window(y_loc, a, w, q, iters: int, gamma: float, force=None) -> WindowTrace:
@@ -299,13 +313,14 @@ def ljsde_window(y_loc, a, w, q, iters: int, gamma: float, force=None) -> Window
     r = np.asarray(y_loc, dtype=np.complex128).copy()
     tr = WindowTrace(coeffs=np.zeros(W2, dtype=np.complex128))
     tr.energy0 = float(np.sum(w * np.abs(r) ** 2))
+    obs = _observed(D)
     for nu in range(iters):
         R = a.conj().T @ (w * r)                             # numerator sum of eq. (10)
         metric = _metric(q, R, D)
         k, gap = _select(metric)
         if force is not None and nu in force:
             k = force[nu]
-        delta = R[k] / D[k]                                  # eq. (16)
+        delta = _step(R, D, obs, k)                          # eq. (16)
         tr.coeffs[k] += gamma * delta                        # eq. (15)
         r = r - gamma * delta * a[:, k]                      # eq. (7) with the step gamma*delta
         tr.picks.append(k)
@@ -332,12 +347,13 @@ def rljsde_window(y_loc, Bm, C, D, q, iters: int, gamma: float, force=None) -> W
     W2 = C.shape[0]
     R = Bm.T @ np.asarray(y_loc, dtype=np.complex128)        # eq. (12), iteration 0
     tr = WindowTrace(coeffs=np.zeros(W2, dtype=np.complex128))
+    obs = _observed(D)
     for nu in range(iters):
         metric = _metric(q, R, D)                            # eq. (11)
         k, gap = _select(metric)
         if force is not None and nu in force:
             k = force[nu]
-        delta = R[k] / D[k]                                  # eq. (16)
+        delta = _step(R, D, obs, k)                          # eq. (16)
         tr.coeffs[k] += gamma * delta                        # eq. (15)
         tr.picks.append(k)
         tr.r_pick.append(R[k])

@@ -43,6 +43,10 @@ def _tile(kind, pr, pc, seed):
         return shape_weights(random_pattern(pr, pc, seed=seed), THREE_QUARTER)
     if kind == "q01":
         return shape_weights(random_pattern(pr, pc, seed=seed), QUARTER)
+    if kind == "band":  # no weight on sensor rows 0..8 of a 16-row period
+        wt = random_weights(pr, pc, seed=seed)
+        wt[:9] = 0.0
+        return wt
     raise ValueError(kind)
 
 
@@ -56,6 +60,9 @@ WCASES = {
     "random_nonrecurrent": (32, 32, None, "random", 32, 4, 40, 0.7, 0.5, False, 36),
     "tq01_w32b4": (48, 40, (4, 4), "tq01", 32, 4, 30, 0.7, 0.5, False, 37),
     "q01_w16b4": (40, 40, (4, 4), "q01", 16, 4, 30, 0.7, 0.5, False, 38),
+    # windows of blocks bi = 2 (mod 8) hold no weighted measurement: no
+    # frequency is observed, the first index is picked with a zero step
+    "band0_w16b4": (32, 16, (16, 4), "band", 16, 4, 20, 0.7, 0.5, False, 39),
 }
 
 
@@ -196,6 +203,7 @@ def test_every_pixel_shape_matches_oracle(L, name):
 
 
 @pytest.mark.parametrize("kind,name", [("weights", "random_w32b4_ragged"), ("weights", "random_w16b8"),
+                                       ("weights", "band0_w16b4"),
                                        ("mask", "half3_w32b4"), ("mask", "full_w32b4"), ("mask", "mask7_w32b4"),
                                        ("mask", "mask4_w32b4")])
 def test_fp32_dense_plans_match_oracle_on_float32_input(L, kind, name):

@@ -112,3 +112,37 @@ def test_scaling_weights_and_measurements_by_two_is_exact():
     a = O.reconstruct(y, None, W=16, B=4, iters=25, form="RL", weights=wt)
     b = O.reconstruct(2.0 * y, None, W=16, B=4, iters=25, form="RL", weights=2.0 * wt)
     np.testing.assert_array_equal(a, b)
+
+
+def test_window_without_weighted_measurements_takes_no_step():
+    """A general layout whose quadrant weights vanish on a whole window leaves
+    every response a_m(sigma, rho) of that window at 0: the weighted least
+    squares of eq. (9) has no term, every step fits equally, and its
+    minimum-norm solution (numpy.linalg.lstsq) is 0. The oracle keeps that
+    window's model at 0 (first index picked, zero step), in both forms, and
+    stays finite elsewhere."""
+    W, B = 16, 4
+    # W = 16, B = 4: window sensor rows start at 2 bi - 3, eight rows; with a
+    # 16-row period whose rows 0..8 carry no weight, blocks bi = 2 (mod 8)
+    # see no weighted measurement
+    wt = random_weights(16, 4, seed=15)
+    wt[:9] = 0.0
+    _, f = synthetic_image(64, 32, seed=15)
+    y = sense_weights(f, wt)
+    nbj = 32 // B
+    for form in ("L", "RL"):
+        out, tr = O.reconstruct(y, None, W=W, B=B, iters=20, form=form, traces=True, weights=wt)
+        assert np.all(np.isfinite(out))
+        for bi in (2, 10):
+            assert np.all(out[B * bi:B * bi + B] == 0.0)
+            for bj in range(nbj):
+                assert tr[(bi, bj)].picks == [0] * 20
+        assert np.any(out[B * 4:B * 4 + B] != 0.0)
+    # the minimum-norm least-squares step of eq. (9) on such a window
+    y_loc, codes, valid = O.local_window(y, wt, 2, 3, W, B)
+    a = O.basis_responses(O.local_measurement_operator_weights(codes, valid, W), O.fourier_basis(W))
+    assert not np.any(a)
+    sw = np.sqrt(O.spatial_weights(W, 0.7) * valid.reshape(-1))
+    for k in (0, 5, 77):
+        step = np.linalg.lstsq((sw * a[:, k])[:, None], sw * y_loc.astype(complex), rcond=None)[0]
+        assert step[0] == 0.0
