@@ -53,6 +53,10 @@ CASES = {
     "q_ones": (40, 40, 4, 32, 4, 25, 0.7, 0.5, True, 8, TQ),
     "gamma_rho": (40, 48, 2, 32, 4, 25, 0.5, 1.5, False, 9, TQ),
     "w16b8_tiny": (8, 24, 2, 16, 8, 12, 0.7, 0.5, False, 10, TQ),
+    # a whole image of one target block (one window, mostly outside the image)
+    "one_block_w32b4": (4, 4, None, 32, 4, 20, 0.7, 0.5, False, 14, TQ),
+    "one_block_w16b8": (8, 8, None, 16, 8, 15, 0.7, 0.5, False, 15, TQ),
+    "single_iteration": (24, 24, 4, 32, 4, 1, 0.7, 0.5, False, 16, TQ),
     # quarter sampling (one transparent quadrant per pixel)
     "quarter_w32b4": (48, 40, 4, 32, 4, 30, 0.7, 0.5, False, 11, QS),
     "quarter_nonrecurrent": (64, 64, None, 32, 4, 60, 0.7, 0.5, False, 12, QS),
