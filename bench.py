@@ -299,7 +299,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(windows are independent; see the sharding notes in DESIGN.md)", file=sys.stderr)
+              "(windows are independent: a frame would split into strips of block rows, one per GPU)", file=sys.stderr)
         sys.exit(2)
 
     wl = WORKLOADS[args.workload]

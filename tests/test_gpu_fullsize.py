@@ -208,8 +208,8 @@ def test_uneven_batch_64_images(L):
 
 
 @pytest.mark.parametrize("variant", ["splitbf16", "state_fp32"])
-def test_frame512_brief_precision_recipes_hold_the_psnr_bar(L, variant):
-    """The brief's precision recipes (split-BF16 window DFT; FP32 loop state)
+def test_frame512_reduced_precision_options_hold_the_psnr_bar(L, variant):
+    """The reduced-precision options (split-BF16 window DFT; FP32 loop state)
     keep the PSNR delta within 0.01 dB on the whole 512x512 frame, but their
     selections diverge from FP64 at near ties in some windows, so they are
     options, not the default (their max-abs is reported, not bounded)."""
