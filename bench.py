@@ -13,7 +13,10 @@ Other workloads (``--workload``): frame2048 (2048x2048 + N(0, 2^2) noise,
 250 iterations), paper1200 (1200x1200, 16x16-sensor tile, 100 iterations),
 batch64 (64 images of uneven size, each with its own pattern of period 2, 4
 or 8, 100 iterations, one batched launch), quarter512 (the 512x512 frame
-under quarter sampling: one transparent quadrant per pixel).
+under quarter sampling: one transparent quadrant per pixel), dense512 (the
+512x512 frame on the dense form: per-class C in device memory, FP64) and
+weights512 (a 512x512 frame under a recurrent 4x4 general layout of per-pixel
+quadrant weights, dense form, FP64).
 
 Prints one JSON line.
 """

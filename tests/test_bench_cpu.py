@@ -1,0 +1,41 @@
+"""Host-side checks of the benchmark script (no GPU): the one-GPU contract and
+the code hash that keys the committed HBM-traffic records."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_code_hash_ignores_comments_and_blank_space():
+    a = "int f(int x) {\n  return x + 1;  // step\n}\n"
+    b = "/* header */\nint f(int x)\n{ return x + 1; }\n\n"
+    c = "int f(int x) { return x + 2; }"
+    assert bench._code_only(a) == bench._code_only(b)
+    assert bench._code_only(a) != bench._code_only(c)
+
+
+def test_traffic_record_is_used_only_for_the_code_it_was_taken_on(tmp_path, monkeypatch):
+    src = tmp_path / "k.hip"
+    src.write_text("__global__ void k() {}\n")
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h = bench.kernel_hash(["k.hip"])
+    (tmp_path / "profiles" / "kernel_traffic.json").write_text(
+        '{"w": {"kernel_hash": "%s", "hbm_bytes_per_launch": 123.0}}' % h)
+    assert bench.load_traffic("w", ["k.hip"]) == 123.0
+    assert bench.load_traffic("other", ["k.hip"]) is None
+    src.write_text("// a comment changes nothing\n__global__ void k() {}\n")
+    assert bench.load_traffic("w", ["k.hip"]) == 123.0
+    src.write_text("__global__ void k() { int x = 0; }\n")
+    assert bench.load_traffic("w", ["k.hip"]) is None
