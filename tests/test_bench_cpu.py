@@ -39,3 +39,19 @@ def test_traffic_record_is_used_only_for_the_code_it_was_taken_on(tmp_path, monk
     assert bench.load_traffic("w", ["k.hip"]) == 123.0
     src.write_text("__global__ void k() { int x = 0; }\n")
     assert bench.load_traffic("w", ["k.hip"]) is None
+
+
+def test_divergence_counts_conjugate_partners_and_reports_the_first_gap():
+    W = bench.W
+    conj = lambda k: ((-(k // W)) % W) * W + (-(k % W)) % W  # noqa: E731
+    picks = {(0, 0): [0, 5, 7], (0, 1): [3, 9, 2], (0, 2): [4, 4, 4]}
+    gaps = {(0, 0): [0.5, 0.1, 0.2], (0, 1): [0.3, 1e-7, 0.4], (0, 2): [0.2, 0.2, 2e-6]}
+    sel = {(0, 0): [0, 5, 7],                 # equal
+           (0, 1): [3, conj(9), conj(2)],     # conjugate partners from the second pick on
+           (0, 2): [4, 4, 6]}                 # a different frequency at the third pick
+    dv = bench.divergence(lambda k: sel[k], picks, gaps)
+    assert dv["diverged"] == 2
+    assert dv["diverged_modulo_conjugation"] == 1
+    g = dv["oracle_top2_gap_at_first_divergence"]
+    assert g["min"] == 1e-7 and g["max"] == 2e-6
+    assert bench.divergence(lambda k: picks[k], picks, gaps)["oracle_top2_gap_at_first_divergence"] is None
