@@ -38,6 +38,8 @@ sys.path.insert(0, ROOT)
 from synth import batch_cases, make_case, random_weights, sense_weights, synthetic_image  # noqa: E402
 
 W, B, RHO, GAMMA = 32, 4, 0.7, 0.5
+FP64_TOL = 1e-9                   # FP64 against the oracle: max-abs
+FP32_TOL, PSNR_TOL = 0.05, 0.01   # FP32 against the oracle: max-abs (grey levels), PSNR delta (dB)
 FLOPS_PER_FREQ_ITER = 30          # factorised form: projection 18, metric 4, update 8
 PEAK_FP32_VALU = 157.3e12         # MI355X FP32 vector peak (packed), FLOP/s
 KERNEL_SOURCES = ["paper_2205_02646_amd/csrc/ljsde_mixed.hip", "paper_2205_02646_amd/csrc/ljsde_device.h",
@@ -276,6 +278,7 @@ def run_dense(args, wl, cases):
         quality["diverged_windows_vs_oracle_sample"] = dv["diverged"]
         quality["diverged_windows_vs_oracle_sample_modulo_conjugation"] = dv["diverged_modulo_conjugation"]
         quality["oracle_top2_gap_at_first_divergence"] = dv["oracle_top2_gap_at_first_divergence"]
+        quality["bar_met"] = quality["maxabs_dense_vs_oracle_sample"] <= FP64_TOL
     col_bytes = W * W * 16
     stream_bytes = nwin * iters * col_bytes  # one column of C per window-iteration (eq. (17))
     algo = n_cols * col_bytes + 8 * y.numel() + 8 * px
@@ -474,6 +477,9 @@ def main():
                         "diverged_windows_fp32_vs_oracle_sample_modulo_conjugation":
                             dv["diverged_modulo_conjugation"],
                         "oracle_top2_gap_at_first_divergence": dv["oracle_top2_gap_at_first_divergence"]})
+        # the value stands only where the FP32 result holds the parity bar
+        quality["bar_met"] = (quality["maxabs_fp32_vs_oracle_sample"] <= FP32_TOL
+                              and quality["psnr_delta_fp32_vs_oracle_sample_db"] <= PSNR_TOL)
         if runs64:
             e64 = max(float(np.max(np.abs(o64[B * i:B * i + B, B * j:B * j + B] - blk)))
                       for (i, j), blk in oracle64_blocks.items())
@@ -501,7 +507,8 @@ def main():
                    "name": args.workload, "images": len(cases), "megapixels": mp, "window": W, "block": B,
                    "iters": iters, "windows": nwin},
         "fp64_plain": ({"value": mp / (ms64 * 1e-3), "unit": "MP/s", "ms_per_step": ms64} if ms64 else None),
-        "speedup_fp32_batched_vs_fp64_plain": (ms64 / ms32 if ms64 else None),
+        # reported only where the FP32 result holds the parity bar (unknown without the oracle)
+        "speedup_fp32_batched_vs_fp64_plain": (ms64 / ms32 if ms64 and quality.get("bar_met", True) else None),
         "launch": launch,
         "setup_ms": {"plans": 1e3 * plan_s, "first_batch_call": 1e3 * first_s, "autotune": 1e3 * tune_s},
         "quality": quality,
