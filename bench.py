@@ -42,6 +42,11 @@ FP64_TOL = 1e-9                   # FP64 against the oracle: max-abs
 FP32_TOL, PSNR_TOL = 0.05, 0.01   # FP32 against the oracle: max-abs (grey levels), PSNR delta (dB)
 FLOPS_PER_FREQ_ITER = 30          # factorised form: projection 18, metric 4, update 8
 PEAK_FP32_VALU = 157.3e12         # MI355X FP32 vector peak (packed), FLOP/s
+PEAK_LDS = 128 * 256 * 2.4e9      # LDS bytes/s taken as 128 B/clk per CU, 256 CUs at 2.4 GHz
+# LDS reads of the FP32 kernel per window-iteration: each of 64 lanes reads, for
+# its 4 positions, the shifted spectra of 4 orientations (16 B each) and its
+# q/D and twiddles (2 x 16 B)
+LDS_BYTES_PER_WIN_ITER = 64 * 4 * (4 * 16 + 2 * 16)
 KERNEL_SOURCES = ["paper_2205_02646_amd/csrc/ljsde_mixed.hip", "paper_2205_02646_amd/csrc/ljsde_device.h",
                   "paper_2205_02646_amd/csrc/ljsde_internal.h"]
 
@@ -519,6 +524,10 @@ def main():
                      "algorithmic_flops_per_launch": flops,
                      "peak_unpacked": PEAK_FP32_VALU / 2e12,
                      "frac_of_peak_unpacked": 2 * achieved / PEAK_FP32_VALU,
+                     "lds": {"bytes_per_window_iteration": LDS_BYTES_PER_WIN_ITER,
+                             "achieved_TBps": nwin * iters * LDS_BYTES_PER_WIN_ITER / (ms32 * 1e-3) / 1e12,
+                             "peak_TBps": PEAK_LDS / 1e12,
+                             "frac": nwin * iters * LDS_BYTES_PER_WIN_ITER / (ms32 * 1e-3) / PEAK_LDS},
                      "note": "algorithmic flops: 30 per frequency and iteration (projection 18, metric 4, "
                              "update 8) x W^2 x iterations x windows. peak: the published FP32 vector "
                              "peak, which counts packed FP32; this code is built with packed FP32 "

@@ -144,7 +144,9 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols,
  * and the per-pixel weights; C of eq. (14) is built from them on the device.
  * Frequencies that leave no trace in a window (D of eq. (13) is 0 in exact
  * arithmetic, e.g. equal weights on all four quadrants at sigma = W/2; in
- * FP64 at most 1e-13 of the window's largest D) are never selected.
+ * FP64 at most 1e-13 of the window's largest D) are never selected. A
+ * window whose weights are all 0 observes no frequency: every iteration picks
+ * frequency 0 with a zero step, and its block of the output is 0.
  * Returns a pattern id >= 0, or a negative status. Needs no GPU.
  */
 int ljsde_plan_weights(const double *weights, int pat_rows, int pat_cols,
