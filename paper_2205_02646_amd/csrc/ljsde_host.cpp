@@ -26,6 +26,8 @@
 #include <tuple>
 #include <vector>
 
+#include <unistd.h>
+
 #include "../../include/ljsde.h"
 #include "ljsde_internal.h"
 
@@ -618,19 +620,30 @@ void load_tune_cache() {
     }
 }
 
+// Written to a temporary file beside the cache and renamed over it, so that
+// processes sharing the cache never read a partly written file.
 void save_tune_cache() {
     const char *path = getenv("LJSDE_TUNE_CACHE");
     if (!path) return;
-    std::ofstream f(path);
-    if (!f) return;
-    f << "{\n";
-    size_t i = 0;
-    for (auto &kv : g_tuned) {
-        f << "  \"" << kv.first << "\" : [" << kv.second.waves_per_block << ", " << kv.second.chunk << ", "
-          << kv.second.fewer_blocks << "]"
-          << (++i < g_tuned.size() ? "," : "") << "\n";
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long long)getpid());
+    {
+        std::ofstream f(tmp);
+        if (!f) return;
+        f << "{\n";
+        size_t i = 0;
+        for (auto &kv : g_tuned) {
+            f << "  \"" << kv.first << "\" : [" << kv.second.waves_per_block << ", " << kv.second.chunk << ", "
+              << kv.second.fewer_blocks << "]"
+              << (++i < g_tuned.size() ? "," : "") << "\n";
+        }
+        f << "}\n";
+        if (!f) {
+            f.close();
+            std::remove(tmp.c_str());
+            return;
+        }
     }
-    f << "}\n";
+    if (std::rename(tmp.c_str(), path) != 0) std::remove(tmp.c_str());
 }
 
 int grid_for(const BatchState &b, const TuneChoice &c, int *grid) {
