@@ -169,6 +169,8 @@ int ljsde_set_energy_floor(int pattern_id, double tau);
  *  out           device, (2*sensor_rows) x (2*sensor_cols), same dtype;
  *                every pixel is written.
  *  stream        hipStream_t or NULL.
+ * Both buffers must be device (or managed) memory of the current device: a
+ * host pointer is LJSDE_EINVAL, and nothing is launched.
  * FP64 plans run one launch with one wavefront per window; FP32 plans run
  * the persistent batched kernel with a batch of one.
  */
@@ -201,7 +203,9 @@ typedef struct {
  * stream, kept until a plan of the batch is released; launches on different
  * streams may overlap). All jobs must use FP32 plans of the factorised form
  * with the same window, block and iteration count. `jobs` is host memory,
- * read during the call only; an empty batch is LJSDE_EINVAL.
+ * read during the call only; an empty batch is LJSDE_EINVAL, and so is a
+ * job whose measurements or out are not device memory (checked whenever a
+ * job's buffers change; nothing is launched then).
  */
 int ljsde_reconstruct_batch(const ljsde_job *jobs, int n_jobs, void *stream);
 

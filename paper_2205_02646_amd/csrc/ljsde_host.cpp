@@ -715,6 +715,30 @@ int build_groups(BatchState &b, int nw) {
     return LJSDE_OK;
 }
 
+// A caller's buffer must be device (or managed) memory of the current device:
+// a kernel handed a host pointer would fault. job < 0 names no batch job.
+static int check_device_buffer(const void *ptr, const char *what, int job) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipPointerAttribute_t a{};
+    const hipError_t e = hipPointerGetAttributes(&a, ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();  // the query's error is not the caller's
+        if (job >= 0) return fail(LJSDE_EINVAL, "job %d: %s is not device memory", job, what);
+        return fail(LJSDE_EINVAL, "%s is not device memory", what);
+    }
+    const bool device = a.type == hipMemoryTypeDevice && a.device == dev;
+    const bool managed = a.type == hipMemoryTypeManaged || a.isManaged;
+    if (!device && !managed) {
+        if (job >= 0)
+            return fail(LJSDE_EINVAL, "job %d: %s is not memory of device %d (memory type %d, device %d)", job,
+                        what, dev, (int)a.type, a.device);
+        return fail(LJSDE_EINVAL, "%s is not memory of device %d (memory type %d, device %d)", what, dev,
+                    (int)a.type, a.device);
+    }
+    return LJSDE_OK;
+}
+
 // Builds (or finds) the batch state for this shape, refreshes the device job
 // table if the buffers changed, and returns it.
 int prepare_batch(const ljsde_job *jobs, int n, void *stream, BatchState **out) {
@@ -800,6 +824,13 @@ int prepare_batch(const ljsde_job *jobs, int n, void *stream, BatchState **out) 
         }
     }
     if (changed) {
+        for (int i = 0; i < n; ++i) {
+            if ((st = check_device_buffer(jobs[i].measurements, "measurements", i)) ||
+                (st = check_device_buffer(jobs[i].out, "out", i))) {
+                for (int k = 0; k < n; ++k) b->host_jobs[k].y = b->host_jobs[k].out = nullptr;  // re-check next call
+                return st;
+            }
+        }
         if (stream) HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
         HIP_TRY(hipMemcpy(b->d_jobs, b->host_jobs.data(), sizeof(KJob) * n, hipMemcpyHostToDevice));
     }
@@ -1094,6 +1125,9 @@ static int reconstruct_impl(const void *y, int Ms, int Ns, int id, void *out, in
     if (st) return st;
     st = ensure_device(*p, *s);
     if (st) return st;
+    if ((st = check_device_buffer(y, "measurements", -1)) || (st = check_device_buffer(out, "out", -1)) ||
+        (sel && (st = check_device_buffer(sel, "selections", -1))))
+        return st;
     KParams k = make_params(*p);
     KJob j = make_job(*s, y, out, sel, 0);
     int e = 0;

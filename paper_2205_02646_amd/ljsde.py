@@ -154,6 +154,14 @@ def _as_input(y, dtype):
     return y
 
 
+def _check_out(y, out, dtype):
+    import torch
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.device == y.device):
+        raise TypeError("out must be a CUDA (HIP) tensor on the device of the measurements")
+    if out.shape != (2 * y.shape[0], 2 * y.shape[1]) or out.dtype != dtype or not out.is_contiguous():
+        raise TypeError("out has the wrong shape, dtype or layout")
+
+
 def reconstruct(y, pid: int, out=None, fp64: Optional[bool] = None, stream=None, selections=None):
     """Reconstruct one image. ``y`` is a contiguous 2-D device tensor (float32
     for FP32 plans, float64 for FP64 plans); returns ``out`` (2R x 2C)."""
@@ -165,8 +173,8 @@ def reconstruct(y, pid: int, out=None, fp64: Optional[bool] = None, stream=None,
     R, C = y.shape
     if out is None:
         out = torch.empty((2 * R, 2 * C), dtype=dtype, device=y.device)
-    elif out.shape != (2 * R, 2 * C) or out.dtype != dtype or not out.is_contiguous():
-        raise TypeError("out has the wrong shape, dtype or layout")
+    else:
+        _check_out(y, out, dtype)
     if selections is None:
         _check(lib().ljsde_reconstruct(y.data_ptr(), R, C, pid, out.data_ptr(), _stream(stream)))
     else:
@@ -204,16 +212,23 @@ def reconstruct_batch(items: Iterable, stream=None) -> None:
     """``items``: sequence of (y, plan_id, out) with float32 device tensors."""
     import torch
     items = list(items)
-    for y, _, out in items:
-        _as_input(y, torch.float32)
-        if out.dtype != torch.float32 or out.shape != (2 * y.shape[0], 2 * y.shape[1]) or not out.is_contiguous():
-            raise TypeError("out has the wrong shape, dtype or layout")
+    _check_items(items)
     arr = _jobs(items)
     _check(lib().ljsde_reconstruct_batch(arr, len(items), _stream(stream)))
 
 
+def _check_items(items):
+    import torch
+    for y, _, out in items:
+        _as_input(y, torch.float32)
+        _check_out(y, out, torch.float32)
+
+
 def autotune(items: Iterable, stream=None) -> None:
+    """Time the launch variants of the batched path on ``items`` (as for
+    ``reconstruct_batch``) and keep the fastest for batches of that shape."""
     items = list(items)
+    _check_items(items)
     arr = _jobs(items)
     _check(lib().ljsde_autotune(arr, len(items), _stream(stream)))
 

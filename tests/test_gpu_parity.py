@@ -362,3 +362,34 @@ def test_failed_allocation_reports_enomem_and_leaves_no_partial_state(L, form, m
     ref = O.reconstruct(y, case["tile"], iters=20, form="RL")
     assert np.max(np.abs(out - ref)) <= (FP64_TOL if fp64 else 0.05)
     L.release(pid)
+
+
+def test_host_buffers_are_refused_before_any_launch(L):
+    """Measurements and output must be device memory: the binding refuses CPU
+    tensors, and the C ABI itself refuses host pointers (LJSDE_EINVAL, no
+    kernel launched), for single calls and batches; a valid call afterwards
+    runs normally."""
+    import ctypes
+    c = make_case(24, 24, 4, seed=90)
+    y = _dev(c["y"].astype(np.float32), np.float32)
+    pid = L.plan(c["tile"], iters=10)
+    good = L.reconstruct(y, pid).cpu().numpy()
+    with pytest.raises(TypeError):
+        L.reconstruct(y, pid, out=torch.empty((24, 24), dtype=torch.float32))
+    with pytest.raises(TypeError):
+        L.reconstruct(y.cpu(), pid)
+    with pytest.raises(TypeError):
+        L.reconstruct_batch([(y, pid, torch.empty((24, 24), dtype=torch.float32))])
+    host = np.zeros((24, 24), np.float32)
+    hp = ctypes.c_void_p(host.ctypes.data)
+    lib = L.lib()
+    assert lib.ljsde_reconstruct(y.data_ptr(), 12, 12, pid, hp, None) == L.EINVAL
+    assert "not" in L.last_error() and "device" in L.last_error()
+    assert lib.ljsde_reconstruct(hp, 12, 12, pid, y.data_ptr(), None) == L.EINVAL
+    jobs = (L.Job * 1)(L.Job(y.data_ptr(), 12, 12, pid, host.ctypes.data))
+    assert lib.ljsde_reconstruct_batch(jobs, 1, None) == L.EINVAL
+    assert lib.ljsde_reconstruct_batch(jobs, 1, None) == L.EINVAL   # checked again, not cached
+    torch.cuda.synchronize()
+    assert np.array_equal(L.reconstruct(y, pid).cpu().numpy(), good)
+    assert not np.any(host)
+    L.release(pid)
