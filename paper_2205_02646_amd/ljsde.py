@@ -166,9 +166,12 @@ def reconstruct(y, pid: int, out=None, fp64: Optional[bool] = None, stream=None,
     """Reconstruct one image. ``y`` is a contiguous 2-D device tensor (float32
     for FP32 plans, float64 for FP64 plans); returns ``out`` (2R x 2C)."""
     import torch
-    if fp64 is None:
-        fp64 = y.dtype == torch.float64
-    dtype = torch.float64 if fp64 else torch.float32
+    # the element type follows the plan: the C ABI cannot check it, and a
+    # mismatch would make the kernels read and write twice (or half) the bytes
+    plan_fp64 = bool(plan_info(pid)["flags"] & FP64)
+    if fp64 is not None and bool(fp64) != plan_fp64:
+        raise TypeError(f"plan {pid} is an {'FP64' if plan_fp64 else 'FP32'} plan")
+    dtype = torch.float64 if plan_fp64 else torch.float32
     _as_input(y, dtype)
     R, C = y.shape
     if out is None:
@@ -219,7 +222,9 @@ def reconstruct_batch(items: Iterable, stream=None) -> None:
 
 def _check_items(items):
     import torch
-    for y, _, out in items:
+    for y, pid, out in items:
+        if plan_info(pid)["flags"] & FP64:
+            raise TypeError(f"plan {pid} is an FP64 plan: batches take FP32 plans")
         _as_input(y, torch.float32)
         _check_out(y, out, torch.float32)
 

@@ -393,3 +393,26 @@ def test_host_buffers_are_refused_before_any_launch(L):
     assert np.array_equal(L.reconstruct(y, pid).cpu().numpy(), good)
     assert not np.any(host)
     L.release(pid)
+
+
+def test_element_type_follows_the_plan(L):
+    """The binding takes the element type from the plan (float32 for FP32
+    plans, float64 for FP64 plans), so a tensor of the other type is refused
+    instead of being read with the wrong width."""
+    c = make_case(24, 24, 4, seed=91)
+    p32 = L.plan(c["tile"], iters=5)
+    p64 = L.plan(c["tile"], iters=5, fp64=True)
+    y32 = _dev(c["y"].astype(np.float32), np.float32)
+    y64 = _dev(c["y"], np.float64)
+    with pytest.raises(TypeError):
+        L.reconstruct(y64, p32)
+    with pytest.raises(TypeError):
+        L.reconstruct(y32, p64)
+    with pytest.raises(TypeError):
+        L.reconstruct(y32, p32, fp64=True)
+    with pytest.raises(TypeError):
+        L.reconstruct_batch([(y32, p64, torch.empty((24, 24), dtype=torch.float32, device="cuda:0"))])
+    assert L.reconstruct(y32, p32).dtype == torch.float32
+    assert L.reconstruct(y64, p64).dtype == torch.float64
+    L.release(p32)
+    L.release(p64)
