@@ -55,3 +55,4 @@ def test_divergence_counts_conjugate_partners_and_reports_the_first_gap():
     g = dv["oracle_top2_gap_at_first_divergence"]
     assert g["min"] == 1e-7 and g["max"] == 2e-6
     assert bench.divergence(lambda k: picks[k], picks, gaps)["oracle_top2_gap_at_first_divergence"] is None
+
