@@ -52,7 +52,8 @@ enum {
     LJSDE_FP64 = 1,           /* FP64 everywhere: measurements/out are double */
     LJSDE_FP32 = 2,           /* FP32 projections, metric and argmax search; FP64 loop state,
                                  tables, step and energy; an FP32 near tie (relative 1e-4) is
-                                 re-decided in FP64. measurements/out are float */
+                                 re-decided in FP64. out is float; measurements are float,
+                                 or double with LJSDE_INPUT_F64 */
     LJSDE_DFT_SPLITBF16 = 4,  /* FP32 plans, W = 32: window DFT on MFMA with 3-term split-BF16
                                  products and FP32 accumulation instead of FP64 MFMA (relative
                                  error ~2^-16 in the initial state; selections can then
@@ -68,11 +69,16 @@ enum {
                                  keeps R of eq. (12) for all W^2 frequencies and subtracts a
                                  column of C per iteration (eq. (17)). Same results as the
                                  factorised FP64 path; single-image calls only. With
-                                 LJSDE_FP32 the measurements and the output are float (the
-                                 arithmetic stays FP64); not with LJSDE_DFT_SPLITBF16 or
+                                 LJSDE_FP32 the output is float (and the measurements unless
+                                 LJSDE_INPUT_F64; the arithmetic stays FP64); not with
+                                 LJSDE_DFT_SPLITBF16 or
                                  LJSDE_STATE_FP32 */
-    LJSDE_WEIGHTS = 64        /* reported by ljsde_plan_info for plans made by
+    LJSDE_WEIGHTS = 64,       /* reported by ljsde_plan_info for plans made by
                                  ljsde_plan_weights (ignored there, refused by ljsde_plan) */
+    LJSDE_INPUT_F64 = 128     /* FP32 plans: the measurements are double (the output stays
+                                 float). The kernels widen every measurement to FP64 on load,
+                                 so an FP32 plan then sees exactly the input an FP64 plan sees.
+                                 Implied by LJSDE_FP64 */
 };
 
 /*
@@ -137,7 +143,8 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols,
  *            shape's measurement matrix.
  *  window, block, iters, rho, gamma  as for ljsde_plan.
  *  flags     LJSDE_DENSE_C with LJSDE_FP64 (double measurements and output)
- *            or LJSDE_FP32 (float; FP64 arithmetic either way), optionally
+ *            or LJSDE_FP32 (float output, and float measurements unless
+ *            LJSDE_INPUT_F64; FP64 arithmetic either way), optionally
  *            LJSDE_Q_ONES; no pixel shape. Without LJSDE_DENSE_C ->
  *            LJSDE_EUNSUPPORTED.
  * Per class the tables hold the ten spectra S_qq' = DFT(w A_q A_q') (q <= q')
@@ -164,10 +171,11 @@ int ljsde_set_energy_floor(int pattern_id, double tau);
 /*
  * ljsde_reconstruct -- reconstruct one image (Sec. IV eqs. (11)-(18) per
  * target block).
- *  measurements  device, sensor_rows x sensor_cols, float (FP32 plan) or
- *                double (FP64 plan). Sides must be multiples of B/2.
- *  out           device, (2*sensor_rows) x (2*sensor_cols), same dtype;
- *                every pixel is written.
+ *  measurements  device, sensor_rows x sensor_cols, double (FP64 plans and
+ *                FP32 plans with LJSDE_INPUT_F64) or float (other FP32
+ *                plans). Sides must be multiples of B/2.
+ *  out           device, (2*sensor_rows) x (2*sensor_cols), double (FP64
+ *                plans) or float (FP32 plans); every pixel is written.
  *  stream        hipStream_t or NULL.
  * Both buffers must be device (or managed) memory of the current device: a
  * host pointer is LJSDE_EINVAL, and nothing is launched.
@@ -189,7 +197,8 @@ int ljsde_reconstruct_diag(const void *measurements, int sensor_rows, int sensor
 
 /* one image of a batch */
 typedef struct {
-    const void *measurements; /* device, as for ljsde_reconstruct */
+    const void *measurements; /* device, as for ljsde_reconstruct (double or float by the
+                                 job's plan: jobs of one batch may differ) */
     int sensor_rows;
     int sensor_cols;
     int pattern_id;           /* FP32 plans with equal window, block and iters */

@@ -139,8 +139,8 @@ struct DenseLds {
 
 // One wavefront per window. SHAPE is a pixel-shape mask or SHAPE_GENERAL
 // (per-pixel quadrant weights: P_q of every quadrant, R = sum_q conj(e_q) P_q).
-// IO is the element type of the measurements and the output (FP32 plans:
-// float; the arithmetic is FP64 either way).
+// IO is the element type of the output (FP32 plans: float; the arithmetic is
+// FP64 either way); the measurements are double or float by the job's flag.
 template <int WS, int SHAPE, typename IO>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void dense_kernel(
     KParams p, KJob j, const double2 *__restrict__ Cd, const int *__restrict__ order) {
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void de
     constexpr bool GENERAL = SHAPE == SHAPE_GENERAL;
     constexpr int PSHAPE = GENERAL ? SHAPE_QUARTER : SHAPE;  // Q_q = P_q
     const double *Aw = GENERAL ? (const double *)(tb + p.lay.offA) : nullptr;
-    const double e0 = window_prologue<double, WS, GENERAL, IO>(p, j, bi, bj, codes, ldsX, ldsC, ldsS, P, Aw);
+    const double e0 = window_prologue<double, WS, GENERAL>(p, j, bi, bj, codes, ldsX, ldsC, ldsS, P, Aw);
 
     // R(0) of eq. (12) through the factorised projection, and q / D
     const double *ew = p.c.ew;

@@ -3,7 +3,15 @@
 
 #include <hip/hip_runtime.h>
 
+#include "ljsde_internal.h"
+
 namespace ljsde {
+
+// Measurement i of a job (row-major), widened to FP64: double or float
+// storage by the job's wave-uniform flag.
+__device__ __forceinline__ double load_measurement(const KJob &j, size_t i) {
+    return j.y64 ? ((const double *)j.y)[i] : (double)((const float *)j.y)[i];
+}
 
 template <typename T>
 struct C2 {

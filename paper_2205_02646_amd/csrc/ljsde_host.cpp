@@ -517,9 +517,10 @@ KParams make_params(const Plan &p) {
     return k;
 }
 
-KJob make_job(const SizeSet &s, const void *y, void *out, int16_t *sel, long long win_begin) {
+KJob make_job(const Plan &p, const SizeSet &s, const void *y, void *out, int16_t *sel, long long win_begin) {
     KJob j{};
     j.y = y;
+    j.y64 = (p.flags & (LJSDE_FP64 | LJSDE_INPUT_F64)) != 0 ? 1 : 0;
     j.out = out;
     j.tables = s.d_tables;
     j.rowcls = s.d_rowcls;
@@ -786,7 +787,7 @@ int prepare_batch(const ljsde_job *jobs, int n, void *stream, BatchState **out) 
             if (st) return st;
             st = ensure_device(*p, *s);
             if (st) return st;
-            b->host_jobs.push_back(make_job(*s, nullptr, nullptr, nullptr, total));
+            b->host_jobs.push_back(make_job(*p, *s, nullptr, nullptr, nullptr, total));
             b->sizes.push_back(s);
             total += (long long)s->nbi * s->nbj;
             n_classes = std::max(n_classes, s->n_classes());
@@ -851,8 +852,7 @@ int launch_batch_eager(BatchState &b, const TuneChoice &c, int grid, void *strea
     return LJSDE_OK;
 }
 
-int capture_graph(BatchState &b) {
-    if (!g_capture_stream) HIP_TRY(hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking));
+void drop_graph(BatchState &b) {
     if (b.exec) {
         (void)hipGraphExecDestroy(b.exec);
         b.exec = nullptr;
@@ -861,8 +861,22 @@ int capture_graph(BatchState &b) {
         (void)hipGraphDestroy(b.graph);
         b.graph = nullptr;
     }
+}
+
+// Captures the batch's launch for its current choice; the work list is
+// (re)built for that choice first, so the graph never refers to a list that
+// the autotuner replaced.
+int capture_graph(BatchState &b) {
+    if (!g_capture_stream) HIP_TRY(hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking));
+    drop_graph(b);
+    int st = grid_for(b, b.choice, &b.grid);
+    if (st) return st;
+    if (!b.state_fp32) {
+        st = build_groups(b, b.choice.waves_per_block);
+        if (st) return st;
+    }
     HIP_TRY(hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal));
-    int st = launch_batch_eager(b, b.choice, b.grid, g_capture_stream);
+    st = launch_batch_eager(b, b.choice, b.grid, g_capture_stream);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(g_capture_stream, &g);
     if (st) {
@@ -873,6 +887,26 @@ int capture_graph(BatchState &b) {
     b.graph = g;
     HIP_TRY(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
     return LJSDE_OK;
+}
+
+// Frees the batch states whose jobs use this plan (their keys list the
+// pattern ids as "id:RxC;"), after the work in flight has completed.
+void drop_batches_of(int pattern_id) {
+    const std::string pref = std::to_string(pattern_id) + ":";
+    bool synced = false;
+    for (auto it = g_batches.begin(); it != g_batches.end();) {
+        const std::string &k = it->first;
+        const bool uses = k.compare(0, pref.size(), pref) == 0 || k.find(";" + pref) != std::string::npos;
+        if (!uses) {
+            ++it;
+            continue;
+        }
+        if (!synced) {
+            (void)hipDeviceSynchronize();
+            synced = true;
+        }
+        it = g_batches.erase(it);
+    }
 }
 
 int run_batch(const ljsde_job *jobs, int n, void *stream) {
@@ -894,7 +928,7 @@ using namespace ljsde;
 
 extern "C" {
 
-int ljsde_version(void) { return 10100; }  // 1.1: ljsde_plan_weights, LJSDE_WEIGHTS, every pixel-shape mask
+int ljsde_version(void) { return 10200; }  // 1.2: LJSDE_INPUT_F64 (1.1: ljsde_plan_weights, every pixel-shape mask)
 
 int ljsde_plan_info(int pattern_id, int *window, int *block, int *iters, unsigned *flags) {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -952,7 +986,7 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, i
     for (long long i = 0; i < (long long)pat_rows * pat_cols; ++i)
         if (pattern[i] > 3) return fail(LJSDE_EINVAL, "pattern code %d at %lld not in 0..3", pattern[i], i);
     const unsigned known = LJSDE_FP64 | LJSDE_FP32 | LJSDE_DFT_SPLITBF16 | LJSDE_Q_ONES | LJSDE_STATE_FP32 |
-                           LJSDE_DENSE_C | LJSDE_SHAPE(15);
+                           LJSDE_DENSE_C | LJSDE_INPUT_F64 | LJSDE_SHAPE(15);
     if (flags & ~known) return fail(LJSDE_EINVAL, "unknown flags 0x%x", flags & ~known);
     if (((flags & LJSDE_FP64) != 0) == ((flags & LJSDE_FP32) != 0))
         return fail(LJSDE_EINVAL, "exactly one of LJSDE_FP64 / LJSDE_FP32 is required");
@@ -1016,7 +1050,7 @@ int ljsde_plan_weights(const double *weights, int pat_rows, int pat_cols, int wi
     for (long long i = 0; i < n; ++i)
         if (!std::isfinite(weights[i])) return fail(LJSDE_EINVAL, "weight %lld is not finite", i);
     const unsigned known = LJSDE_FP64 | LJSDE_FP32 | LJSDE_DFT_SPLITBF16 | LJSDE_Q_ONES | LJSDE_STATE_FP32 |
-                           LJSDE_DENSE_C | LJSDE_SHAPE(15) | LJSDE_WEIGHTS;
+                           LJSDE_DENSE_C | LJSDE_INPUT_F64 | LJSDE_SHAPE(15) | LJSDE_WEIGHTS;
     if (flags & ~known) return fail(LJSDE_EINVAL, "unknown flags 0x%x", flags & ~known);
     if (flags & LJSDE_SHAPE(15)) return fail(LJSDE_EINVAL, "a pixel shape does not apply to a weights plan");
     if (((flags & LJSDE_FP64) != 0) == ((flags & LJSDE_FP32) != 0))
@@ -1053,7 +1087,13 @@ int ljsde_set_energy_floor(int pattern_id, double tau) {
     int st = get_plan(pattern_id, &p);
     if (st) return st;
     if (!(tau >= 0.0 && tau < 1.0)) return fail(LJSDE_EINVAL, "tau %g must be in [0, 1)", tau);
-    p->tau = tau;
+    if (tau != p->tau) {
+        p->tau = tau;
+        // batch states hold the kernel parameters (and their graphs a copy of
+        // them) from their creation: drop those of this plan, so that the next
+        // batched call rebuilds them with the new floor
+        drop_batches_of(pattern_id);
+    }
     return ok();
 }
 
@@ -1129,7 +1169,7 @@ static int reconstruct_impl(const void *y, int Ms, int Ns, int id, void *out, in
         (sel && (st = check_device_buffer(sel, "selections", -1))))
         return st;
     KParams k = make_params(*p);
-    KJob j = make_job(*s, y, out, sel, 0);
+    KJob j = make_job(*p, *s, y, out, sel, 0);
     int e = 0;
     if (p->flags & LJSDE_DENSE_C) {
         st = ensure_dense(*p, *s, stream);
@@ -1179,6 +1219,11 @@ int ljsde_autotune(const ljsde_job *jobs, int n_jobs, void *stream) {
     HIP_TRY(hipEventCreate(&e1));
     float best_ms = 1e30f;
     TuneChoice best = b->choice;
+    // the candidates rebuild the work list, which the captured graph refers
+    // to: drop the graph now (the next batched call re-captures it for the
+    // batch's choice, also when the tuning fails part-way)
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    drop_graph(*b);
     for (const TuneChoice &c : cands) {
         int grid = 0;
         st = grid_for(*b, c, &grid);
@@ -1210,12 +1255,6 @@ int ljsde_autotune(const ljsde_job *jobs, int n_jobs, void *stream) {
     (void)hipEventDestroy(e1);
     if (st) return st;
     b->choice = best;
-    st = grid_for(*b, best, &b->grid);
-    if (st) return st;
-    if (!b->state_fp32) {
-        st = build_groups(*b, best.waves_per_block);
-        if (st) return st;
-    }
     g_tuned[b->tune_key] = best;
     save_tune_cache();
     st = capture_graph(*b);
@@ -1240,13 +1279,7 @@ int ljsde_release(int pattern_id) {
     // work in flight may still read the plan's tables
     if (p->d_consts) (void)hipDeviceSynchronize();
     // batches that reference this plan hold device pointers into its tables
-    for (auto it = g_batches.begin(); it != g_batches.end();) {
-        bool uses = false;
-        std::string k = it->first;
-        std::string pref = std::to_string(pattern_id) + ":";
-        if (k.compare(0, pref.size(), pref) == 0 || k.find(";" + pref) != std::string::npos) uses = true;
-        it = uses ? g_batches.erase(it) : std::next(it);
-    }
+    drop_batches_of(pattern_id);
     for (auto &kv : p->sizes) {
         SizeSet &s = *kv.second;
         if (s.d_tables) (void)hipFree(s.d_tables);

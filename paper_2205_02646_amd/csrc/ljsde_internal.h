@@ -56,6 +56,8 @@ struct KJob {
     const int *colcls;             // [nbj] column key index
     int16_t *sel;                  // [nwin][iters] or null
     int Ms, Ns, nbi, nbj, ncolk;
+    int y64;                       // measurements are double (FP64 plans, and FP32 plans
+                                   // made with LJSDE_INPUT_F64), else float
     long long win_begin;           // first global window index of this job
 };
 

@@ -85,7 +85,6 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
     // ---- gather the sensor tile, weighted (absent pixels -> 0) -------------
     const int rs = (p.B * bi - p.off) / 2;
     const int cs = (p.B * bj - p.off) / 2;
-    const float *Y = (const float *)j.y;
     double e0 = 0.0;
     for (int m = lane; m < NPOS; m += 64) {
         const int ip = m / WS, jp = m % WS;
@@ -93,7 +92,7 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         signed char code = codes[m];
         double x = 0.0;
         if (code >= 0 && gi >= 0 && gi < j.Ms && gj >= 0 && gj < j.Ns) {
-            const double yv = (double)Y[(size_t)gi * j.Ns + gj];
+            const double yv = load_measurement(j, (size_t)gi * j.Ns + gj);
             x = p.c.w[m] * yv;
             e0 += x * yv;
         } else {

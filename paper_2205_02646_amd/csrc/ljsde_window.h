@@ -23,8 +23,8 @@ struct WinLds {
 // (codes) and, for WS = 8 only (the VALU DFT), ldsS [NPOS * 8] (stage).
 // WEIGHTED (general layouts): P holds P_q = DFT(w * y * A_q) for the class's
 // per-pixel quadrant weights Aw [NPOS][4] instead of the code-masked spectra.
-// YT: element type of the measurements (float or double).
-template <typename T, int WS, bool WEIGHTED = false, typename YT = T>
+// The measurements are double or float by the job's flag (read as FP64).
+template <typename T, int WS, bool WEIGHTED = false>
 __device__ __forceinline__ double window_prologue(const KParams &p, const KJob &j, int bi, int bj,
                                                   const signed char *codes, T *ldsX, signed char *ldsC, T *ldsS,
                                                   C2<T> P[][4], const double *Aw = nullptr) {
@@ -39,7 +39,6 @@ __device__ __forceinline__ double window_prologue(const KParams &p, const KJob &
     // ---- gather the window's sensor tile (absent pixels -> 0) -------------
     const int rs = (p.B * bi - p.off) / 2;
     const int cs = (p.B * bj - p.off) / 2;
-    const YT *Y = (const YT *)j.y;
     double e0 = 0.0;
     for (int m = lane; m < NPOS; m += 64) {
         const int ip = m / WS, jp = m % WS;
@@ -47,7 +46,7 @@ __device__ __forceinline__ double window_prologue(const KParams &p, const KJob &
         signed char code = codes[m];
         T x = T(0);
         if (code >= 0 && gi >= 0 && gi < j.Ms && gj >= 0 && gj < j.Ns) {
-            const double yv = (double)Y[(size_t)gi * j.Ns + gj];
+            const double yv = load_measurement(j, (size_t)gi * j.Ns + gj);
             const double wy = p.c.w[m] * yv;
             x = (T)wy;
             e0 += wy * yv;

@@ -36,6 +36,7 @@ def SHAPE(mask: int) -> int:
 STATE_FP32 = 16
 DENSE_C = 32
 WEIGHTS = 64  # reported by plan_info for plans of plan_weights
+INPUT_F64 = 128  # FP32 plans: double measurements (float output)
 
 _NAMES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOMEM: "ENOMEM", EHIP: "EHIP", EBADID: "EBADID"}
 
@@ -105,31 +106,35 @@ def version() -> int:
 
 def plan(pattern, window: int = 32, block: int = 4, iters: int = 100, rho: float = 0.7,
          gamma: float = 0.5, fp64: bool = False, splitbf16: bool = False, q_ones: bool = False,
-         state_fp32: bool = False, shape: int = 0, dense_c: bool = False) -> int:
+         state_fp32: bool = False, shape: int = 0, dense_c: bool = False, input_f64: bool = False) -> int:
     """Register a plan for a pattern tile of quadrant codes; returns its id.
     ``shape`` is the pixel-shape mask (0 or SHAPE_THREE_QUARTER: L-shaped
     pixels; SHAPE_QUARTER: one transparent quadrant per pixel). ``dense_c``
     selects the dense form (FP64 arithmetic; float32 I/O for FP32 plans): per
-    class the full C of eq. (14) in device memory, R as the loop state."""
+    class the full C of eq. (14) in device memory, R as the loop state.
+    ``input_f64``: an FP32 plan that takes float64 measurements (the output
+    stays float32)."""
     pat = np.ascontiguousarray(np.asarray(pattern, dtype=np.uint8))
     if pat.ndim != 2:
         raise ValueError("pattern must be 2-D")
     flags = ((FP64 if fp64 else FP32) | (DFT_SPLITBF16 if splitbf16 else 0) | (Q_ONES if q_ones else 0)
-             | (STATE_FP32 if state_fp32 else 0) | (DENSE_C if dense_c else 0) | SHAPE(shape))
+             | (STATE_FP32 if state_fp32 else 0) | (DENSE_C if dense_c else 0) | SHAPE(shape)
+             | (INPUT_F64 if input_f64 else 0))
     return _check(lib().ljsde_plan(pat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), pat.shape[0],
                                    pat.shape[1], window, block, iters, rho, gamma, flags))
 
 
 def plan_weights(weights, window: int = 32, block: int = 4, iters: int = 100, rho: float = 0.7,
-                 gamma: float = 0.5, q_ones: bool = False, fp64: bool = True) -> int:
+                 gamma: float = 0.5, q_ones: bool = False, fp64: bool = True, input_f64: bool = False) -> int:
     """Register a plan for a general layout: ``weights`` is a [rows, cols, 4]
     tile of per-pixel quadrant weights (quadrant 2a + b of the footprint).
     Runs on the dense form in FP64; ``fp64=False`` takes float32
-    measurements and returns float32 images."""
+    measurements and returns float32 images (float64 measurements with
+    ``input_f64``)."""
     wt = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
     if wt.ndim != 3 or wt.shape[2] != 4:
         raise ValueError("weights must be a [rows, cols, 4] tile")
-    flags = (FP64 if fp64 else FP32) | DENSE_C | (Q_ONES if q_ones else 0)
+    flags = (FP64 if fp64 else FP32) | DENSE_C | (Q_ONES if q_ones else 0) | (INPUT_F64 if input_f64 else 0)
     return _check(lib().ljsde_plan_weights(wt.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), wt.shape[0],
                                            wt.shape[1], window, block, iters, rho, gamma, flags))
 
@@ -162,22 +167,31 @@ def _check_out(y, out, dtype):
         raise TypeError("out has the wrong shape, dtype or layout")
 
 
-def reconstruct(y, pid: int, out=None, fp64: Optional[bool] = None, stream=None, selections=None):
-    """Reconstruct one image. ``y`` is a contiguous 2-D device tensor (float32
-    for FP32 plans, float64 for FP64 plans); returns ``out`` (2R x 2C)."""
+def _dtypes(pid: int):
+    """(measurement dtype, output dtype) of a plan: the element types follow
+    the plan, which the C ABI cannot check; a mismatch would make the kernels
+    read or write twice (or half) the bytes."""
     import torch
-    # the element type follows the plan: the C ABI cannot check it, and a
-    # mismatch would make the kernels read and write twice (or half) the bytes
-    plan_fp64 = bool(plan_info(pid)["flags"] & FP64)
+    flags = plan_info(pid)["flags"]
+    out = torch.float64 if flags & FP64 else torch.float32
+    return (torch.float64 if flags & (FP64 | INPUT_F64) else torch.float32), out
+
+
+def reconstruct(y, pid: int, out=None, fp64: Optional[bool] = None, stream=None, selections=None):
+    """Reconstruct one image. ``y`` is a contiguous 2-D device tensor (float64
+    for FP64 plans and FP32 plans with ``input_f64``, else float32); returns
+    ``out`` (2R x 2C; float64 for FP64 plans, else float32)."""
+    import torch
+    ydt, odt = _dtypes(pid)
+    plan_fp64 = odt == torch.float64
     if fp64 is not None and bool(fp64) != plan_fp64:
         raise TypeError(f"plan {pid} is an {'FP64' if plan_fp64 else 'FP32'} plan")
-    dtype = torch.float64 if plan_fp64 else torch.float32
-    _as_input(y, dtype)
+    _as_input(y, ydt)
     R, C = y.shape
     if out is None:
-        out = torch.empty((2 * R, 2 * C), dtype=dtype, device=y.device)
+        out = torch.empty((2 * R, 2 * C), dtype=odt, device=y.device)
     else:
-        _check_out(y, out, dtype)
+        _check_out(y, out, odt)
     if selections is None:
         _check(lib().ljsde_reconstruct(y.data_ptr(), R, C, pid, out.data_ptr(), _stream(stream)))
     else:
@@ -212,7 +226,8 @@ def _jobs(items: Sequence) -> ctypes.Array:
 
 
 def reconstruct_batch(items: Iterable, stream=None) -> None:
-    """``items``: sequence of (y, plan_id, out) with float32 device tensors."""
+    """``items``: sequence of (y, plan_id, out) device tensors of FP32 plans
+    (y float32, or float64 for plans with ``input_f64``; out float32)."""
     import torch
     items = list(items)
     _check_items(items)
@@ -225,8 +240,9 @@ def _check_items(items):
     for y, pid, out in items:
         if plan_info(pid)["flags"] & FP64:
             raise TypeError(f"plan {pid} is an FP64 plan: batches take FP32 plans")
-        _as_input(y, torch.float32)
-        _check_out(y, out, torch.float32)
+        ydt, odt = _dtypes(pid)
+        _as_input(y, ydt)
+        _check_out(y, out, odt)
 
 
 def autotune(items: Iterable, stream=None) -> None:

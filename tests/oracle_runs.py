@@ -39,6 +39,38 @@ def run_blocks(y, tile, blocks, procs=None, **kw):
     return {(bi, bj): (blk, pk, gp) for part in parts for bi, bj, blk, pk, gp in part}
 
 
+_SHARED = []  # inputs of run_many, inherited by the forked workers
+
+
+def _work_many(args):
+    k, blocks, kw = args
+    y, tile = _SHARED[k]
+    return k, _work((y, tile, blocks, kw))
+
+
+def run_many(jobs, procs=None, chunk=32, **kw):
+    """Oracle on several images at once: ``jobs`` is a list of (y, tile,
+    blocks); returns one {(bi, bj): (block, picks, top-2 gaps)} per job. The
+    images reach the workers by fork, not by pickling."""
+    kw.setdefault("form", "RL")
+    procs = procs or min(os.cpu_count() or 1, 16)
+    _SHARED[:] = [(y, tile) for y, tile, _ in jobs]
+    tasks = []
+    for k, (_, _, blocks) in enumerate(jobs):
+        blocks = list(blocks)
+        tasks += [(k, blocks[i:i + chunk], kw) for i in range(0, len(blocks), chunk)]
+    try:
+        with mp.get_context("fork").Pool(procs) as pool:
+            parts = pool.map(_work_many, tasks, chunksize=1)
+    finally:
+        _SHARED[:] = []
+    out = [dict() for _ in jobs]
+    for k, part in parts:
+        for bi, bj, blk, pk, gp in part:
+            out[k][(bi, bj)] = (blk, pk, gp)
+    return out
+
+
 def centre_blocks(n_blocks_r: int, n_blocks_c: int, crop_px: int, B: int = 4):
     nr, nc = crop_px // B, crop_px // B
     r0, c0 = (n_blocks_r - nr) // 2, (n_blocks_c - nc) // 2

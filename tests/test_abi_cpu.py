@@ -217,6 +217,20 @@ def test_shape_flags_are_kept_and_default_to_three_quarter():
         ljsde.release(p)
 
 
+def test_float64_input_flag_is_accepted_and_kept():
+    """LJSDE_INPUT_F64 (FP32 plans that read double measurements) is a known
+    flag of both plan constructors and is reported back; the ABI version
+    names it."""
+    assert ljsde.version() >= 10200
+    p0 = ljsde.plan(TILE, input_f64=True)
+    p1 = ljsde.plan(TILE, input_f64=True, dense_c=True)
+    p2 = ljsde.plan_weights(np.ones((2, 2, 4)), fp64=False, input_f64=True)
+    for p in (p0, p1, p2):
+        assert ljsde.plan_info(p)["flags"] & ljsde.INPUT_F64
+        assert not ljsde.plan_info(p)["flags"] & ljsde.FP64
+        ljsde.release(p)
+
+
 @pytest.mark.parametrize("W,bi,bj,shape", [(32, 10, 9, 0xE), (32, 0, 3, 0xE), (16, 1, 5, 0xE),
                                            (32, 10, 9, 0x1), (16, 0, 2, 0x1)])
 def test_class_tables_reproduce_dense_C_and_D(W, bi, bj, shape):

@@ -56,3 +56,19 @@ def test_divergence_counts_conjugate_partners_and_reports_the_first_gap():
     assert g["min"] == 1e-7 and g["max"] == 2e-6
     assert bench.divergence(lambda k: picks[k], picks, gaps)["oracle_top2_gap_at_first_divergence"] is None
 
+
+
+def test_cpu_baseline_spreads_its_sample_over_the_images_and_keys_it_by_image():
+    """The oracle sample of a batch covers every image, and each block comes
+    back under (image, block row, block column) with the oracle's own result."""
+    from oracle import ljsde_oracle as O
+    from synth import make_case
+    imgs = [make_case(16, 16, 2, seed=3), make_case(12, 20, 4, seed=4)]
+    rec, res, picks, gaps = bench.cpu_baseline([(c["y"], c["tile"], 0xE, None) for c in imgs], 4, 6, label="t")
+    assert {k for k, _, _ in res} == {0, 1}
+    assert len(res) == 6 and set(res) == set(picks) == set(gaps)
+    for (k, bi, bj), blk in res.items():
+        ref, tr = O.reconstruct(imgs[k]["y"], imgs[k]["tile"], iters=4, form="RL", blocks=[(bi, bj)], traces=True)
+        assert abs(blk - ref[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4]).max() == 0.0
+        assert list(picks[(k, bi, bj)]) == tr[(bi, bj)].picks
+    assert rec["kind"] == "oracle" and rec["cores"] >= 1 and rec["value"] > 0

@@ -6,13 +6,15 @@ The oracle computes every window of the 512x512 frame, the 256x256 centre
 crop of the larger frames (their windows read the full measurements), and
 random samples plus border windows elsewhere. Bars: FP64 <= 1e-9 max-abs;
 FP32 <= 0.05 max-abs and <= 0.01 dB PSNR delta, no diverged selection
-sequence against the oracle on the same float32 input.
+sequence against the oracle on the same input. FP32 plans read the float64
+measurements the oracle reads (``input_f64``); the 8192x8192 frame, a float32
+image, also runs on float32 measurements against the oracle on those values.
 """
 import numpy as np
 import pytest
 
 from synth import QUARTER, batch_cases, make_case
-from tests.oracle_runs import centre_blocks, run_blocks, sample_blocks
+from tests.oracle_runs import centre_blocks, run_blocks, run_many, sample_blocks
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -44,10 +46,12 @@ def _gather(out, blocks):
     return {(bi, bj): out[B * bi:B * bi + B, B * bj:B * bj + B] for bi, bj in blocks}
 
 
-def _fp32_batched(L, y32, tile, iters, shape=0):
-    pid = L.plan(tile, iters=iters, shape=shape)
-    y = torch.from_numpy(y32).to("cuda:0")
-    out = torch.empty((2 * y32.shape[0], 2 * y32.shape[1]), dtype=torch.float32, device="cuda:0")
+def _fp32_batched(L, yh, tile, iters, shape=0):
+    """FP32 plan on the persistent batched launch (and its graph replay);
+    float64 measurements are read as they are (``input_f64``)."""
+    pid = L.plan(tile, iters=iters, shape=shape, input_f64=yh.dtype == np.float64)
+    y = torch.from_numpy(yh).to("cuda:0")
+    out = torch.empty((2 * yh.shape[0], 2 * yh.shape[1]), dtype=torch.float32, device="cuda:0")
     L.reconstruct_batch([(y, pid, out)])
     L.reconstruct_batch([(y, pid, out)])         # graph replay
     o = out.cpu().numpy().astype(np.float64)
@@ -61,7 +65,9 @@ def _fp64_plain(L, y64, tile, iters, shape=0):
     return o
 
 
-def _check_fp32(L, pid, y, o32, ref, clean, iters, label):
+def _fp32_stats(L, pid, y, o32, ref, clean):
+    """max-abs, PSNR delta (against the clean image, over the checked blocks)
+    and diverged fraction of an FP32 result against the oracle's blocks."""
     blocks = sorted(ref)
     err = max(float(np.max(np.abs(o32[B * i:B * i + B, B * j:B * j + B] - ref[(i, j)][0]))) for i, j in blocks)
     got = np.concatenate([o32[B * i:B * i + B, B * j:B * j + B].ravel() for i, j in blocks])
@@ -72,7 +78,13 @@ def _check_fp32(L, pid, y, o32, ref, clean, iters, label):
     sel = sel.cpu().numpy()
     nbj = o32.shape[1] // B
     div = np.mean([not np.array_equal(sel[i * nbj + j], ref[(i, j)][1]) for i, j in blocks])
-    print(f"{label}: FP32 {len(blocks)} windows, max-abs {err:.3e}, PSNR delta {dpsnr:.2e} dB, "
+    return err, dpsnr, div
+
+
+def _check_fp32(L, pid, y, o32, ref, clean, iters, label):
+    err, dpsnr, div = _fp32_stats(L, pid, y, o32, ref, clean)
+    src = "float64" if y.dtype == torch.float64 else "float32"
+    print(f"{label}: FP32 ({src} input) {len(ref)} windows, max-abs {err:.3e}, PSNR delta {dpsnr:.2e} dB, "
           f"diverged {div:.5f}", flush=True)
     assert err <= FP32_TOL
     assert dpsnr <= 0.01
@@ -88,15 +100,12 @@ def _check_fp64(o64, ref, label):
 def test_frame512_whole(L):
     """512x512 frame, random 4x4-sensor tile, 100 iterations (the benchmark workload)."""
     c = make_case(512, 512, 4, seed=0)
-    y32 = c["y"].astype(np.float32)
     blocks = [(i, j) for i in range(128) for j in range(128)]
-    ref32 = run_blocks(y32.astype(np.float64), c["tile"], blocks, iters=100)
-    pid, y, o32 = _fp32_batched(L, y32, c["tile"], 100)
-    _check_fp32(L, pid, y, o32, ref32, c["clean"], 100, "frame512")
+    ref = run_blocks(c["y"], c["tile"], blocks, iters=100)
+    pid, y, o32 = _fp32_batched(L, c["y"], c["tile"], 100)
+    _check_fp32(L, pid, y, o32, ref, c["clean"], 100, "frame512")
     L.release(pid)
-    sample = sample_blocks(128, 128, 400, seed=1)
-    ref64 = run_blocks(c["y"], c["tile"], sample, iters=100)
-    _check_fp64(_fp64_plain(L, c["y"], c["tile"], 100), ref64, "frame512")
+    _check_fp64(_fp64_plain(L, c["y"], c["tile"], 100), ref, "frame512")
 
 
 def test_frame512_dense_form_equals_factorised_form(L):
@@ -124,20 +133,19 @@ def test_frame512_dense_form_equals_factorised_form(L):
 def test_frame2048_noisy_crop(L):
     """2048x2048 frame with N(0, 2^2) noise, random 8x8-sensor tile, 250 iterations."""
     c = make_case(2048, 2048, 8, seed=0, noise=2.0)
-    y32 = c["y"].astype(np.float32)
     crop = centre_blocks(512, 512, 256)
-    ref32 = run_blocks(y32.astype(np.float64), c["tile"], crop, iters=250)
-    pid, y, o32 = _fp32_batched(L, y32, c["tile"], 250)
-    _check_fp32(L, pid, y, o32, ref32, c["clean"], 250, "frame2048 crop")
-    L.release(pid)
     sample = sample_blocks(512, 512, 150, seed=2)
-    ref64 = run_blocks(c["y"], c["tile"], sample, iters=250)
-    _check_fp64(_fp64_plain(L, c["y"], c["tile"], 250), ref64, "frame2048")
+    ref = run_blocks(c["y"], c["tile"], sorted(set(crop) | set(sample)), iters=250)
+    pid, y, o32 = _fp32_batched(L, c["y"], c["tile"], 250)
+    _check_fp32(L, pid, y, o32, {k: ref[k] for k in crop}, c["clean"], 250, "frame2048 crop")
+    L.release(pid)
+    _check_fp64(_fp64_plain(L, c["y"], c["tile"], 250), {k: ref[k] for k in sample}, "frame2048")
 
 
 def test_frame8192_many_classes_crop(L):
     """8192x8192 frame, random 16x16-sensor tile (64 interior classes, 256 with
-    the border ones), 250 iterations."""
+    the border ones), 250 iterations. A float32 image: the FP32 plan reads
+    float32 measurements, and the oracle runs on those same values."""
     c = make_case(8192, 8192, 16, seed=0)
     y32 = c["y"].astype(np.float32)
     crop = centre_blocks(2048, 2048, 256)
@@ -156,69 +164,87 @@ def test_quarter_sampling_frame1024_crop(L):
     pixel), random 8x8-sensor tile, 100 iterations: every window of the
     256x256 centre crop and a sample in FP64."""
     c = make_case(1024, 1024, 8, seed=3, shape=QUARTER)
-    y32 = c["y"].astype(np.float32)
     crop = centre_blocks(256, 256, 256)
-    ref32 = run_blocks(y32.astype(np.float64), c["tile"], crop, iters=100, shape=QUARTER)
-    pid, y, o32 = _fp32_batched(L, y32, c["tile"], 100, shape=QUARTER)
-    _check_fp32(L, pid, y, o32, ref32, c["clean"], 100, "quarter 1024 crop")
-    L.release(pid)
     sample = sample_blocks(256, 256, 150, seed=5)
-    ref64 = run_blocks(c["y"], c["tile"], sample, iters=100, shape=QUARTER)
-    _check_fp64(_fp64_plain(L, c["y"], c["tile"], 100, shape=QUARTER), ref64, "quarter 1024")
+    ref = run_blocks(c["y"], c["tile"], sorted(set(crop) | set(sample)), iters=100, shape=QUARTER)
+    pid, y, o32 = _fp32_batched(L, c["y"], c["tile"], 100, shape=QUARTER)
+    _check_fp32(L, pid, y, o32, {k: ref[k] for k in crop}, c["clean"], 100, "quarter 1024 crop")
+    L.release(pid)
+    _check_fp64(_fp64_plain(L, c["y"], c["tile"], 100, shape=QUARTER), {k: ref[k] for k in sample},
+                "quarter 1024")
 
 
 def test_paper_shape_1200(L):
     """The paper's frame shape: 1200x1200, recurrent pattern of period 32 px."""
     c = make_case(1200, 1200, 16, seed=0)
-    y32 = c["y"].astype(np.float32)
     sample = sample_blocks(300, 300, 600, seed=4)
-    ref32 = run_blocks(y32.astype(np.float64), c["tile"], sample, iters=100)
-    pid, y, o32 = _fp32_batched(L, y32, c["tile"], 100)
-    _check_fp32(L, pid, y, o32, ref32, c["clean"], 100, "paper 1200")
+    ref = run_blocks(c["y"], c["tile"], sample, iters=100)
+    pid, y, o32 = _fp32_batched(L, c["y"], c["tile"], 100)
+    _check_fp32(L, pid, y, o32, ref, c["clean"], 100, "paper 1200")
     L.release(pid)
-    ref64 = run_blocks(c["y"], c["tile"], sample[:200], iters=100)
-    _check_fp64(_fp64_plain(L, c["y"], c["tile"], 100), ref64, "paper 1200")
+    _check_fp64(_fp64_plain(L, c["y"], c["tile"], 100), ref, "paper 1200")
 
 
 def test_uneven_batch_64_images(L):
     """64 images of uneven size, each with its own pattern of period 2, 4 or 8,
-    in one persistent graph-captured launch; 100 iterations."""
+    in one persistent graph-captured launch; 100 iterations, FP32 plans on the
+    float64 measurements. Per image, 256 random windows plus border and corner
+    windows against the oracle: max-abs, PSNR delta over the checked blocks
+    and diverged selection sequences; the plain FP64 path on 8 of the images."""
     cases = batch_cases(64, seed=0)
     items = []
     for k, c in enumerate(cases):
-        y = torch.from_numpy(c["y"].astype(np.float32)).to("cuda:0")
-        pid = L.plan(c["tile"], iters=100)
+        y = torch.from_numpy(c["y"]).to("cuda:0")
+        pid = L.plan(c["tile"], iters=100, input_f64=True)
         out = torch.empty((2 * y.shape[0], 2 * y.shape[1]), dtype=torch.float32, device="cuda:0")
         items.append((y, pid, out))
     L.reconstruct_batch(items)
     L.reconstruct_batch(items)
     torch.cuda.synchronize()
-    worst = 0.0
-    for k, (c, (y, pid, out)) in enumerate(zip(cases, items)):
-        nbr, nbc = out.shape[0] // B, out.shape[1] // B
-        sample = sample_blocks(nbr, nbc, 24, seed=10 + k)
-        ref = run_blocks(c["y"].astype(np.float32).astype(np.float64), c["tile"], sample, iters=100, procs=8)
-        o = out.cpu().numpy().astype(np.float64)
-        err = max(float(np.max(np.abs(o[B * i:B * i + B, B * j:B * j + B] - ref[(i, j)][0]))) for i, j in sample)
-        worst = max(worst, err)
+    samples = [sample_blocks(out.shape[0] // B, out.shape[1] // B, 256, seed=10 + k)
+               for k, (_, _, out) in enumerate(items)]
+    refs = run_many([(c["y"], c["tile"], s) for c, s in zip(cases, samples)], iters=100)
+    worst, worst_dpsnr, n_div, n_win = 0.0, 0.0, 0, 0
+    for k, (c, (y, pid, out), ref) in enumerate(zip(cases, items, refs)):
+        err, dpsnr, div = _fp32_stats(L, pid, y, out.cpu().numpy().astype(np.float64), ref, c["clean"])
+        worst, worst_dpsnr = max(worst, err), max(worst_dpsnr, dpsnr)
+        n_div += int(round(div * len(ref)))
+        n_win += len(ref)
         assert err <= FP32_TOL, (k, err)
-    print(f"uneven batch: 64 images, worst sampled max-abs {worst:.3e}", flush=True)
+        assert dpsnr <= 0.01, (k, dpsnr)
+        assert div == 0.0, (k, div)
+    print(f"uneven batch: 64 images, {n_win} windows, worst max-abs {worst:.3e}, worst PSNR delta "
+          f"{worst_dpsnr:.2e} dB, diverged {n_div}", flush=True)
     for _, pid, _ in items:
         L.release(pid)
+    del items
+    for k in range(0, 64, 8):
+        c = cases[k]
+        _check_fp64(_fp64_plain(L, c["y"], c["tile"], 100), refs[k], f"uneven batch image {k}")
+
+
+DESIGN_NUMBERS = {
+    "splitbf16": "the split-BF16 window DFT perturbs the initial state by ~1e-5 relative; on the 512x512 "
+                 "frame 11% of the windows then pick a different sequence (near ties with top-2 gaps "
+                 "0..6.6e-4), up to 8.3 grey levels",
+    "state_fp32": "the FP32 loop state drifts by ~1e-5 relative over 100 iterations; on the 512x512 frame "
+                  "0.085% of the windows flip a near tie (top-2 gaps 6.9e-9..6.7e-6), up to 2.5 grey levels",
+}
 
 
 @pytest.mark.parametrize("variant", ["splitbf16", "state_fp32"])
-def test_frame512_reduced_precision_options_hold_the_psnr_bar(L, variant):
+@pytest.mark.xfail(strict=True, reason="reduced-precision options miss the 0.05 max-abs bar")
+def test_frame512_reduced_precision_options_hold_the_fp32_bar(L, variant):
     """The reduced-precision options (split-BF16 window DFT; FP32 loop state)
-    keep the PSNR delta within 0.01 dB on the whole 512x512 frame, but their
-    selections diverge from FP64 at near ties in some windows, so they are
-    options, not the default (their max-abs is reported, not bounded)."""
+    against the FP32 bar on the whole 512x512 frame: max-abs <= 0.05, PSNR
+    delta <= 0.01 dB, no diverged selection sequence. Expected to fail (strict
+    xfail, so that a fix shows): greedy selection is discontinuous, and their
+    rounding flips near ties. The numbers are printed."""
     c = make_case(512, 512, 4, seed=0)
-    y32 = c["y"].astype(np.float32)
     blocks = [(i, j) for i in range(128) for j in range(128)]
-    ref = run_blocks(y32.astype(np.float64), c["tile"], blocks, iters=100)
-    pid = L.plan(c["tile"], iters=100, **{variant: True})
-    y = torch.from_numpy(y32).to("cuda:0")
+    ref = run_blocks(c["y"], c["tile"], blocks, iters=100)
+    pid = L.plan(c["tile"], iters=100, input_f64=True, **{variant: True})
+    y = torch.from_numpy(c["y"]).to("cuda:0")
     out = torch.empty((512, 512), dtype=torch.float32, device="cuda:0")
     L.reconstruct_batch([(y, pid, out)])
     o = out.cpu().numpy().astype(np.float64)
@@ -243,7 +269,8 @@ def test_frame512_reduced_precision_options_hold_the_psnr_bar(L, variant):
     gap_txt = f", top-2 gap at first divergence {min(gaps):.1e}..{max(gaps):.1e}" if gaps else ""
     print(f"{variant}: max-abs {err.max():.3e}, windows above 0.05: {np.mean(err > 0.05):.5f}, "
           f"PSNR delta {dpsnr:.2e} dB, diverged windows {raw / n:.5f} (modulo conjugation {canon / n:.5f})"
-          f"{gap_txt}", flush=True)
-    assert dpsnr <= 0.01
-    assert canon <= raw
+          f"{gap_txt} [{DESIGN_NUMBERS[variant]}]", flush=True)
     L.release(pid)
+    assert dpsnr <= 0.01
+    assert err.max() <= FP32_TOL
+    assert raw == 0

@@ -1,9 +1,10 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
 
 Bars (fixed by the project goal): FP64 mode <= 1e-9 max-abs; FP32 mode
-<= 0.05 grey levels max-abs and <= 0.01 dB PSNR delta. FP32 plans consume
-float32 measurements, so their oracle runs on those same values (rounded to
-float32, then computed in FP64). Selection sequences must be equal: ties
+<= 0.05 grey levels max-abs and <= 0.01 dB PSNR delta. FP32 plans run on the
+same float64 measurements as the oracle (plans with ``input_f64``), and also
+on float32 measurements, against the oracle run on those same values (rounded
+to float32, then computed in FP64). Selection sequences must be equal: ties
 (metrics within a relative 1e-10) go to the lowest frequency index on both
 sides. The all-FP32 variant decides in FP32 and is held to the output bars
 only.
@@ -105,25 +106,33 @@ def test_fp64_matches_oracle(L, name, dense):
     L.release(pid)
 
 
+@pytest.mark.parametrize("input_f64", [True, False], ids=["f64in", "f32in"])
 @pytest.mark.parametrize("state_fp32", [False, True], ids=["fp64state", "fp32state"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_fp32_matches_oracle(L, name, state_fp32):
+def test_fp32_matches_oracle(L, name, state_fp32, input_f64):
+    """FP32 plans against the FP64 oracle on the same measurements: float64
+    (the oracle's own input) or float32."""
     if state_fp32 and CASES[name][-1] != THREE_QUARTER:
         pytest.skip("the all-FP32 variant exists for three-quarter sampling only")
     c, ref, tr, kw = _cached(name)
-    ref32 = c["ref32"]
-    pid = L.plan(c["tile"], state_fp32=state_fp32, **kw)
-    out, sel = L.reconstruct_diag(_dev(c["y32"], np.float32), pid)
-    out_b = L.reconstruct(_dev(c["y32"], np.float32), pid)          # batched persistent path
+    if input_f64:
+        y, ydt, ref_out, ref_tr = c["y"], np.float64, ref, tr
+    else:
+        y, ydt, ref_out, ref_tr = c["y32"], np.float32, c["ref32"], c["tr32"]
+    pid = L.plan(c["tile"], state_fp32=state_fp32, input_f64=input_f64, **kw)
+    out, sel = L.reconstruct_diag(_dev(y, ydt), pid)
+    out_b = L.reconstruct(_dev(y, ydt), pid)          # batched persistent path
+    assert out.dtype == torch.float32
     assert torch.equal(out, out_b)
     out = out.cpu().numpy().astype(np.float64)
     sel = sel.cpu().numpy()
-    err = np.max(np.abs(out - ref32))
-    dpsnr = abs(_psnr(out, c["clean"]) - _psnr(ref32, c["clean"]))
+    err = np.max(np.abs(out - ref_out))
+    dpsnr = abs(_psnr(out, c["clean"]) - _psnr(ref_out, c["clean"]))
     W = kw["window"]
     nbj = out.shape[1] // kw["block"]
-    div = np.mean([list(sel[w]) != c["tr32"][divmod(w, nbj)].picks for w in range(sel.shape[0])])
-    print(f"{name}: FP32 max-abs {err:.3e}, PSNR delta {dpsnr:.2e} dB, diverged windows {div:.4f}")
+    div = np.mean([list(sel[w]) != ref_tr[divmod(w, nbj)].picks for w in range(sel.shape[0])])
+    print(f"{name}: FP32 ({'float64' if input_f64 else 'float32'} input) max-abs {err:.3e}, "
+          f"PSNR delta {dpsnr:.2e} dB, diverged windows {div:.4f}")
     assert err <= FP32_TOL
     assert dpsnr <= 0.01
     if not state_fp32:
@@ -414,5 +423,52 @@ def test_element_type_follows_the_plan(L):
         L.reconstruct_batch([(y32, p64, torch.empty((24, 24), dtype=torch.float32, device="cuda:0"))])
     assert L.reconstruct(y32, p32).dtype == torch.float32
     assert L.reconstruct(y64, p64).dtype == torch.float64
+    # FP32 plans made with input_f64 read float64 measurements, write float32
+    pin = L.plan(c["tile"], iters=5, input_f64=True)
+    with pytest.raises(TypeError):
+        L.reconstruct(y32, pin)
+    with pytest.raises(TypeError):
+        L.reconstruct_batch([(y32, pin, torch.empty((24, 24), dtype=torch.float32, device="cuda:0"))])
+    assert L.reconstruct(y64, pin).dtype == torch.float32
     L.release(p32)
     L.release(p64)
+    L.release(pin)
+
+
+def test_batch_mixes_float32_and_float64_measurements(L):
+    """One batch whose jobs read float32 and float64 measurements (by their
+    plans) gives each job the result of its single-image call."""
+    cases = [make_case(r, c, p, seed=60 + k) for k, (r, c, p) in enumerate([(40, 48, 4), (24, 36, 2), (32, 32, 8)])]
+    items, singles = [], []
+    for k, c in enumerate(cases):
+        f64 = k % 2 == 0
+        pid = L.plan(c["tile"], iters=20, input_f64=f64)
+        y = _dev(c["y"], np.float64) if f64 else _dev(c["y"].astype(np.float32), np.float32)
+        out = torch.empty((2 * y.shape[0], 2 * y.shape[1]), dtype=torch.float32, device="cuda:0")
+        items.append((y, pid, out))
+        singles.append(L.reconstruct_diag(y, pid)[0])
+    L.reconstruct_batch(items)
+    torch.cuda.synchronize()
+    for (y, pid, out), ref in zip(items, singles):
+        assert torch.equal(out, ref)
+        L.release(pid)
+
+
+def test_energy_floor_change_reaches_the_batched_path(L):
+    """A batched call, then a new energy floor, then another batched call: the
+    second call honours the new floor (equal to the diagnostic call, which
+    reads the floor every time)."""
+    c = make_case(40, 40, 4, seed=77)
+    pid = L.plan(c["tile"], iters=60, input_f64=True)
+    y = _dev(c["y"], np.float64)
+    out = torch.empty((80, 80), dtype=torch.float32, device="cuda:0")
+    L.reconstruct_batch([(y, pid, out)])
+    no_floor = out.clone()
+    L.set_energy_floor(pid, 0.02)
+    L.reconstruct_batch([(y, pid, out)])
+    ref, sel = L.reconstruct_diag(y, pid)
+    torch.cuda.synchronize()
+    assert bool((sel < 0).any())               # some window stopped early
+    assert torch.equal(out, ref)
+    assert not torch.equal(out, no_floor)
+    L.release(pid)
