@@ -18,7 +18,10 @@ tile, 250 iterations), frame8192 (8192x8192 float32 image, 16x16-sensor tile,
 under quarter sampling: one transparent quadrant per pixel), dense512 (the
 512x512 frame on the dense form: per-class C in device memory, FP64) and
 weights512 (a 512x512 frame under a recurrent 4x4 general layout of per-pixel
-quadrant weights, dense form, FP64).
+quadrant weights, dense form, FP64), ljsde64 (a 64x64 frame with a
+non-recurrent pattern, plain L-JSDE in FP64: the paper's baseline method) and
+ljsde256 (a 256x256 frame with a recurrent 4x4-sensor pattern, plain L-JSDE),
+each timed beside the recurrent FP64 and FP32 batched paths on the same input.
 
 Prints one JSON line.
 """
@@ -76,6 +79,14 @@ WORKLOADS = {
                        desc="512x512 frame, general layout (random per-pixel quadrant weights, recurrent "
                             "4x4-sensor tile), FP64 dense form"),
 }
+WORKLOADS.update({
+    "ljsde64": dict(kind="frame", rows=64, cols=64, period=None, iters=100, noise=0.0, path="plain_l",
+                    desc="64x64 frame, non-recurrent pattern (every window its own local measurement matrix), "
+                         "plain L-JSDE FP64"),
+    "ljsde256": dict(kind="frame", rows=256, cols=256, period=4, iters=100, noise=0.0, path="plain_l",
+                     desc="256x256 frame, recurrent 4x4-sensor pattern, plain L-JSDE FP64"),
+})
+PEAK_FP64_MFMA = 78.6e12          # MI355X FP64 matrix peak, FLOP/s
 HBM_PEAK_GBPS = 8000.0            # MI355X HBM3E
 DENSE_KERNEL_SOURCES = ["paper_2205_02646_amd/csrc/ljsde_dense.hip", "paper_2205_02646_amd/csrc/ljsde_window.h",
                         "paper_2205_02646_amd/csrc/ljsde_device.h", "paper_2205_02646_amd/csrc/ljsde_internal.h"]
@@ -365,6 +376,110 @@ def run_dense(args, wl, cases):
     print(json.dumps(rec), flush=True)
 
 
+def run_plain_l(args, wl, cases):
+    """Plain L-JSDE (Sec. IV eq. (10) every iteration, residual in the
+    measurement domain), FP64, one launch per step, beside the recurrent FP64
+    path and the FP32 batched path on the same input: their time ratio is the
+    speed-up of the recurrence on this GPU (Sec. V-C compares the same two
+    forms). Roofline: the FP64 MFMA peak against the algorithmic flops of the
+    eq. (10) product (8 per measurement, frequency and iteration)."""
+    iters = wl["iters"]
+    c = cases[0]
+    oracle_rec, oracle_blocks, oracle_picks, oracle_gaps = None, {}, {}, {}
+    if not args.no_oracle:
+        oracle_rec, oracle_blocks, oracle_picks, oracle_gaps = cpu_baseline(
+            [(c["y"], c["tile"], 0xE, None)], iters, min(args.oracle_windows, 256), label=wl["desc"].split(",")[0])
+    import torch
+    from paper_2205_02646_amd import ljsde
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    y = torch.from_numpy(c["y"]).to(dev)
+    rows, cols = 2 * y.shape[0], 2 * y.shape[1]
+    pl = ljsde.plan(c["tile"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA, fp64=True, plain_l=True)
+    pr = ljsde.plan(c["tile"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA, fp64=True)
+    p32 = ljsde.plan(c["tile"], window=W, block=B, iters=iters, rho=RHO, gamma=GAMMA, input_f64=True)
+    ol = torch.empty((rows, cols), dtype=torch.float64, device=dev)
+    orr = torch.empty_like(ol)
+    o32 = torch.empty((rows, cols), dtype=torch.float32, device=dev)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    # the first call builds the basis responses of the image size (not timed)
+    # and records the selections
+    t0 = time.perf_counter()
+    _, sel = ljsde.reconstruct_diag(y, pl, stream=stream)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    sel = sel.cpu().numpy()
+    msl = timed(lambda: ljsde.reconstruct(y, pl, out=ol, stream=stream), args.steps, args.warmup)
+    msr = timed(lambda: ljsde.reconstruct(y, pr, out=orr, stream=stream), max(3, args.steps), 1)
+    ljsde.reconstruct_batch([(y, p32, o32)], stream=stream)
+    ms32 = timed(lambda: ljsde.reconstruct_batch([(y, p32, o32)], stream=stream), max(3, args.steps), 1)
+    ljsde.synchronize(stream)
+    px = rows * cols
+    nwin = (rows // B) * (cols // B)
+    o = ol.cpu().numpy()
+    quality = {"maxabs_plain_l_vs_recurrent_fp64": float(torch.max(torch.abs(ol - orr)))}
+    if oracle_blocks:
+        quality["maxabs_plain_l_vs_oracle_sample"] = max(
+            float(np.max(np.abs(o[B * i:B * i + B, B * j:B * j + B] - blk))) for (_, i, j), blk in oracle_blocks.items())
+        quality["oracle_sample_windows"] = len(oracle_blocks)
+        nbj0 = cols // B
+        dv = divergence(lambda k: sel[k[1] * nbj0 + k[2]], oracle_picks, oracle_gaps)
+        quality["diverged_windows_vs_oracle_sample"] = dv["diverged"]
+        quality["bar_met"] = quality["maxabs_plain_l_vs_oracle_sample"] <= FP64_TOL and dv["diverged"] == 0
+    _, cmap = ljsde.class_map(pl, y.shape[0], y.shape[1])
+    n_classes = int(np.unique(cmap).size)
+    npos = (W // 2) ** 2
+    flops = nwin * iters * 8 * npos * W * W  # eq. (10) numerator: one complex multiply-add per (m, f)
+    achieved = flops / (msl * 1e-3)
+    rec = {
+        "metric": METRIC,
+        "value": px / 1e6 / (msl * 1e-3),
+        "unit": "MP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": msl,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"plain L-JSDE {wl['desc']}, W=32 B=4, {iters} iterations, rho 0.7, gamma 0.5 "
+                               "(FP64 single-image launch)",
+                   "name": args.workload, "images": 1, "megapixels": px / 1e6, "window": W, "block": B,
+                   "iters": iters, "windows": nwin, "classes": n_classes},
+        "recurrent_fp64": {"value": px / 1e6 / (msr * 1e-3), "unit": "MP/s", "ms_per_step": msr},
+        "recurrent_fp32_batched": {"value": px / 1e6 / (ms32 * 1e-3), "unit": "MP/s", "ms_per_step": ms32},
+        "speedup_recurrent_fp64_vs_plain_l": msl / msr,
+        "speedup_recurrent_fp32_batched_vs_plain_l": msl / ms32,
+        "setup_ms": {"first_call_with_basis_build": 1e3 * setup_s},
+        "quality": quality,
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64_MFMA / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
+                     "kernel_hash": kernel_hash(["paper_2205_02646_amd/csrc/ljsde_lplain.hip"]),
+                     "algorithmic_flops_per_launch": flops,
+                     "note": "algorithmic flops: 8 per local measurement, frequency and iteration (the complex "
+                             "multiply-add of the eq. (10) numerator) x windows, on FP64 MFMA; windows of one "
+                             "local measurement matrix share the product, up to 16 per workgroup, so a "
+                             "non-recurrent pattern fills one of the 16 MFMA columns"},
+        "cpu_baseline": oracle_rec,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -388,6 +503,9 @@ def main():
     cases = build_inputs(wl)
     if wl.get("path") == "fp64_dense":
         run_dense(args, wl, cases)
+        return
+    if wl.get("path") == "plain_l":
+        run_plain_l(args, wl, cases)
         return
     # The measurements both paths read: the workload's float64 read-out, or its
     # float32 rounding for a float32 image (frame8192). FP32 plans read float64

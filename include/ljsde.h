@@ -75,10 +75,22 @@ enum {
                                  LJSDE_STATE_FP32 */
     LJSDE_WEIGHTS = 64,       /* reported by ljsde_plan_info for plans made by
                                  ljsde_plan_weights (ignored there, refused by ljsde_plan) */
-    LJSDE_INPUT_F64 = 128     /* FP32 plans: the measurements are double (the output stays
+    LJSDE_INPUT_F64 = 128,    /* FP32 plans: the measurements are double (the output stays
                                  float). The kernels widen every measurement to FP64 on load,
                                  so an FP32 plan then sees exactly the input an FP64 plan sees.
                                  Implied by LJSDE_FP64 */
+    LJSDE_PLAIN_L = 4096      /* FP64 plans: plain L-JSDE (Sec. III; Sec. IV eqs. (4)-(10), (15),
+                                 (16)), the method the recurrent form accelerates. Each window
+                                 keeps its residual in the measurement domain and evaluates the
+                                 numerator of eq. (10) for every basis function in every
+                                 iteration: a product with the dense (W/2)^2 x W^2 matrix of basis
+                                 responses a_m(f) = sum A_m Phi_f, O(W^4) per iteration. The
+                                 responses of every local measurement matrix of an image size are
+                                 built in device memory on its first reconstruction (16 B x
+                                 (W/2)^2 x W^2 per class: 4 MiB at W = 32; LJSDE_ENOMEM if they
+                                 do not fit). Same results as the recurrent form. Single-image
+                                 calls only; not with LJSDE_DENSE_C. Every pixel shape and
+                                 ljsde_plan_weights layouts */
 };
 
 /*
@@ -93,7 +105,7 @@ enum {
  * tables then report the relabelled codes). Masks with two bits (half and
  * diagonal pixels) or four (full pixels) run as their 0/1 quadrant weights on
  * the general-layout dense form (see ljsde_plan_weights): they need
- * LJSDE_DENSE_C, else LJSDE_EUNSUPPORTED, and ljsde_plan_info
+ * LJSDE_DENSE_C (or LJSDE_PLAIN_L), else LJSDE_EUNSUPPORTED, and ljsde_plan_info
  * reports LJSDE_WEIGHTS for them. LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32
  * exist for three-quarter sampling only.
  * Frequencies that no measurement of a window responds to (D of eq. (13) at
@@ -144,9 +156,9 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols,
  *  window, block, iters, rho, gamma  as for ljsde_plan.
  *  flags     LJSDE_DENSE_C with LJSDE_FP64 (double measurements and output)
  *            or LJSDE_FP32 (float output, and float measurements unless
- *            LJSDE_INPUT_F64; FP64 arithmetic either way), optionally
- *            LJSDE_Q_ONES; no pixel shape. Without LJSDE_DENSE_C ->
- *            LJSDE_EUNSUPPORTED.
+ *            LJSDE_INPUT_F64; FP64 arithmetic either way), or LJSDE_PLAIN_L
+ *            with LJSDE_FP64; optionally LJSDE_Q_ONES; no pixel shape.
+ *            Without LJSDE_DENSE_C or LJSDE_PLAIN_L -> LJSDE_EUNSUPPORTED.
  * Per class the tables hold the ten spectra S_qq' = DFT(w A_q A_q') (q <= q')
  * and the per-pixel weights; C of eq. (14) is built from them on the device.
  * Frequencies that leave no trace in a window (D of eq. (13) is 0 in exact

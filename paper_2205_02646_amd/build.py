@@ -26,7 +26,7 @@ HIP_ONLY = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
-SOURCES = ["ljsde_kernels.hip", "ljsde_mixed.hip", "ljsde_dense.hip", "ljsde_host.cpp"]
+SOURCES = ["ljsde_kernels.hip", "ljsde_mixed.hip", "ljsde_dense.hip", "ljsde_lplain.hip", "ljsde_host.cpp"]
 
 
 def _hipcc() -> str:

@@ -95,6 +95,10 @@ struct SizeSet {
     void *d_dense = nullptr;  // dense C of every class (LJSDE_DENSE_C plans), built on first use
     int *d_order = nullptr;   // dense form: window of every workgroup (-1: none), see dense_order
     int order_len = 0;
+    void *d_la = nullptr;      // plain L-JSDE: basis responses a of every class, built on first use
+    void *d_laux = nullptr;    // plain L-JSDE: q/D and 1/D of every class
+    LGroup *d_lgroups = nullptr;  // plain L-JSDE: window groups in launch order
+    int n_lgroups = 0;
 };
 
 struct Plan {
@@ -107,7 +111,7 @@ struct Plan {
     ClassLayout lay{};
     std::vector<double> w, ew, dft, q, H;  // class-independent FP64 tables
     int device = -1;
-    double *d_consts = nullptr;         // w | ew | dft | H
+    double *d_consts = nullptr;         // w | ew | dft | H | q
     std::map<std::pair<int, int>, std::unique_ptr<SizeSet>> sizes;
     bool fp64() const { return (flags & LJSDE_FP64) != 0; }
     bool general() const { return shape == SHAPE_GENERAL; }
@@ -452,6 +456,7 @@ int ensure_device(Plan &p, SizeSet &s) {
         c.insert(c.end(), p.ew.begin(), p.ew.end());
         c.insert(c.end(), p.dft.begin(), p.dft.end());
         c.insert(c.end(), p.H.begin(), p.H.end());
+        c.insert(c.end(), p.q.begin(), p.q.end());
         void *d = nullptr;
         st = dev_alloc(&d, c.size() * sizeof(double));
         if (st) return st;
@@ -513,6 +518,7 @@ KParams make_params(const Plan &p) {
     k.c.ew = p.d_consts + p.w.size();
     k.c.dft = p.d_consts + p.w.size() + p.ew.size();
     k.c.H = p.d_consts + p.w.size() + p.ew.size() + p.dft.size();
+    k.c.q = k.c.H + p.H.size();
     k.lay = p.lay;
     return k;
 }
@@ -647,17 +653,19 @@ void save_tune_cache() {
     if (std::rename(tmp.c_str(), path) != 0) std::remove(tmp.c_str());
 }
 
-int grid_for(const BatchState &b, const TuneChoice &c, int *grid) {
+int grid_for_shape(int ws, bool state_fp32, const TuneChoice &c, int *grid) {
     int dev = 0, ncu = 0, blocks = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int e = b.state_fp32 ? persistent_blocks_per_cu(b.ws, c.waves_per_block, &blocks)
-                               : mixed_blocks_per_cu(b.ws, c.waves_per_block, &blocks);
+    const int e = state_fp32 ? persistent_blocks_per_cu(ws, c.waves_per_block, &blocks)
+                             : mixed_blocks_per_cu(ws, c.waves_per_block, &blocks);
     if (e != 0 || blocks <= 0) return fail(LJSDE_EHIP, "occupancy query failed (%d)", e);
     // a grid below full occupancy can finish a batch in whole rounds
     *grid = ncu * std::max(1, blocks - c.fewer_blocks);
     return LJSDE_OK;
 }
+
+int grid_for(const BatchState &b, const TuneChoice &c, int *grid) { return grid_for_shape(b.ws, b.state_fp32, c, grid); }
 
 // Work list of the persistent FP32 launch: groups of up to nw windows of one
 // class (they share the class tables staged in LDS). Windows are grouped
@@ -665,11 +673,11 @@ int grid_for(const BatchState &b, const TuneChoice &c, int *grid) {
 // each axis (the number of row / column keys bounds that period), so a group
 // is four nearby windows, and the tiles are listed in row-major order. The
 // list is cut into XCD_RANGES contiguous ranges of equal length.
-int build_groups(BatchState &b, int nw) {
-    if (b.groups_nw == nw && b.d_groups) return LJSDE_OK;
-    std::vector<WinGroup> groups;
-    for (size_t ji = 0; ji < b.sizes.size(); ++ji) {
-        const SizeSet &s = *b.sizes[ji];
+void make_group_list(const std::vector<const SizeSet *> &sizes, int nw, std::vector<WinGroup> &groups,
+                     int ranges[XCD_RANGES + 1]) {
+    groups.clear();
+    for (size_t ji = 0; ji < sizes.size(); ++ji) {
+        const SizeSet &s = *sizes[ji];
         const int nck = (int)s.colkeys.size();
         const int tr = std::min(s.nbi, std::max(16, 2 * (int)s.rowkeys.size()));
         const int tc = std::min(s.nbj, std::max(16, 2 * (int)s.colkeys.size()));
@@ -697,8 +705,14 @@ int build_groups(BatchState &b, int nw) {
                 used.clear();
             }
     }
-    int ranges[XCD_RANGES + 1];
     for (int r = 0; r <= XCD_RANGES; ++r) ranges[r] = (int)((long long)groups.size() * r / XCD_RANGES);
+}
+
+int build_groups(BatchState &b, int nw) {
+    if (b.groups_nw == nw && b.d_groups) return LJSDE_OK;
+    std::vector<WinGroup> groups;
+    int ranges[XCD_RANGES + 1];
+    make_group_list(b.sizes, nw, groups, ranges);
     if (b.d_groups) {
         (void)hipFree(b.d_groups);
         b.d_groups = nullptr;
@@ -928,7 +942,7 @@ using namespace ljsde;
 
 extern "C" {
 
-int ljsde_version(void) { return 10200; }  // 1.2: LJSDE_INPUT_F64 (1.1: ljsde_plan_weights, every pixel-shape mask)
+int ljsde_version(void) { return 10300; }  // 1.3: LJSDE_PLAIN_L (1.2: LJSDE_INPUT_F64; 1.1: ljsde_plan_weights, every pixel-shape mask)
 
 int ljsde_plan_info(int pattern_id, int *window, int *block, int *iters, unsigned *flags) {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -986,10 +1000,12 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, i
     for (long long i = 0; i < (long long)pat_rows * pat_cols; ++i)
         if (pattern[i] > 3) return fail(LJSDE_EINVAL, "pattern code %d at %lld not in 0..3", pattern[i], i);
     const unsigned known = LJSDE_FP64 | LJSDE_FP32 | LJSDE_DFT_SPLITBF16 | LJSDE_Q_ONES | LJSDE_STATE_FP32 |
-                           LJSDE_DENSE_C | LJSDE_INPUT_F64 | LJSDE_SHAPE(15);
+                           LJSDE_DENSE_C | LJSDE_INPUT_F64 | LJSDE_SHAPE(15) | LJSDE_PLAIN_L;
     if (flags & ~known) return fail(LJSDE_EINVAL, "unknown flags 0x%x", flags & ~known);
     if (((flags & LJSDE_FP64) != 0) == ((flags & LJSDE_FP32) != 0))
         return fail(LJSDE_EINVAL, "exactly one of LJSDE_FP64 / LJSDE_FP32 is required");
+    if ((flags & LJSDE_PLAIN_L) && (!(flags & LJSDE_FP64) || (flags & LJSDE_DENSE_C)))
+        return fail(LJSDE_EINVAL, "LJSDE_PLAIN_L needs LJSDE_FP64 and excludes LJSDE_DENSE_C");
     if ((flags & (LJSDE_DFT_SPLITBF16 | LJSDE_STATE_FP32)) && (flags & LJSDE_FP64))
         return fail(LJSDE_EINVAL, "LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32 apply to FP32 plans only");
     if ((flags & LJSDE_DENSE_C) && (flags & (LJSDE_DFT_SPLITBF16 | LJSDE_STATE_FP32)))
@@ -1022,9 +1038,10 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, i
     } else {
         // Two or four collected quadrants (half, diagonal and full pixels):
         // their 0/1 quadrant weights through the general-layout dense form.
-        if (!(flags & LJSDE_DENSE_C))
-            return fail(LJSDE_EUNSUPPORTED, "pixel shape mask 0x%x runs on the dense form only (LJSDE_DENSE_C)",
-                        mask);
+        if (!(flags & (LJSDE_DENSE_C | LJSDE_PLAIN_L)))
+            return fail(LJSDE_EUNSUPPORTED,
+                        "pixel shape mask 0x%x runs on the dense form (LJSDE_DENSE_C) or plain L-JSDE "
+                        "(LJSDE_PLAIN_L) only", mask);
         p->quad.resize(n * 4);
         for (size_t i = 0; i < n; ++i)
             for (int q = 0; q < 4; ++q) p->quad[i * 4 + q] = (double)((mask >> (q ^ pattern[i])) & 1);
@@ -1050,7 +1067,7 @@ int ljsde_plan_weights(const double *weights, int pat_rows, int pat_cols, int wi
     for (long long i = 0; i < n; ++i)
         if (!std::isfinite(weights[i])) return fail(LJSDE_EINVAL, "weight %lld is not finite", i);
     const unsigned known = LJSDE_FP64 | LJSDE_FP32 | LJSDE_DFT_SPLITBF16 | LJSDE_Q_ONES | LJSDE_STATE_FP32 |
-                           LJSDE_DENSE_C | LJSDE_INPUT_F64 | LJSDE_SHAPE(15) | LJSDE_WEIGHTS;
+                           LJSDE_DENSE_C | LJSDE_INPUT_F64 | LJSDE_SHAPE(15) | LJSDE_WEIGHTS | LJSDE_PLAIN_L;
     if (flags & ~known) return fail(LJSDE_EINVAL, "unknown flags 0x%x", flags & ~known);
     if (flags & LJSDE_SHAPE(15)) return fail(LJSDE_EINVAL, "a pixel shape does not apply to a weights plan");
     if (((flags & LJSDE_FP64) != 0) == ((flags & LJSDE_FP32) != 0))
@@ -1064,8 +1081,11 @@ int ljsde_plan_weights(const double *weights, int pat_rows, int pat_cols, int wi
     if (!(block == 4 || block == 8))
         return fail(LJSDE_EUNSUPPORTED, "no kernel for block %d (have 4, 8)", block);
     if (iters > 32767) return fail(LJSDE_EUNSUPPORTED, "iters %d above 32767", iters);
-    if (!(flags & LJSDE_DENSE_C))
-        return fail(LJSDE_EUNSUPPORTED, "general layouts run on the dense form only (LJSDE_DENSE_C)");
+    if ((flags & LJSDE_PLAIN_L) && (!(flags & LJSDE_FP64) || (flags & LJSDE_DENSE_C)))
+        return fail(LJSDE_EINVAL, "LJSDE_PLAIN_L needs LJSDE_FP64 and excludes LJSDE_DENSE_C");
+    if (!(flags & (LJSDE_DENSE_C | LJSDE_PLAIN_L)))
+        return fail(LJSDE_EUNSUPPORTED,
+                    "general layouts run on the dense form (LJSDE_DENSE_C) or plain L-JSDE (LJSDE_PLAIN_L) only");
     auto p = std::make_unique<Plan>();
     p->quad.assign(weights, weights + n);
     p->pattern.assign((size_t)pat_rows * pat_cols, 0);
@@ -1154,6 +1174,77 @@ static int ensure_dense(Plan &p, SizeSet &s, void *stream) {
     return LJSDE_OK;
 }
 
+// Window groups of plain L-JSDE: windows sorted by class (row-major inside
+// a class), cut into groups of up to LGROUP windows of one class, and dealt so
+// that workgroup b runs group b / XCD_RANGES of chunk b % XCD_RANGES of that
+// list (workgroups go to the XCDs round-robin): each XCD works through a few
+// classes at a time and their basis responses stay in its L2.
+static std::vector<LGroup> lplain_groups(const SizeSet &s) {
+    const int n = s.nbi * s.nbj, nck = (int)s.colkeys.size();
+    auto cls_of = [&](int w) { return s.rowcls[w / s.nbj] * nck + s.colcls[w % s.nbj]; };
+    std::vector<int> win(n);
+    for (int i = 0; i < n; ++i) win[i] = i;
+    std::stable_sort(win.begin(), win.end(), [&](int a, int b) { return cls_of(a) < cls_of(b); });
+    std::vector<LGroup> list;
+    for (int i = 0; i < n;) {
+        LGroup g{};
+        g.cls = cls_of(win[i]);
+        while (i < n && g.count < LGROUP && cls_of(win[i]) == g.cls) g.win[g.count++] = win[i++];
+        for (int k = g.count; k < LGROUP; ++k) g.win[k] = g.win[0];
+        list.push_back(g);
+    }
+    const int ng = (int)list.size();
+    const int cs = (ng + XCD_RANGES - 1) / XCD_RANGES;
+    std::vector<LGroup> order((size_t)cs * XCD_RANGES);  // count 0: idle
+    for (int x = 0; x < XCD_RANGES; ++x)
+        for (int i = 0; i < cs && x * cs + i < ng; ++i) order[(size_t)i * XCD_RANGES + x] = list[x * cs + i];
+    return order;
+}
+
+// Basis responses and normalisers of plain L-JSDE for every class of a size
+// set, built on the device on first use; LJSDE_ENOMEM when they would not fit
+// in the free device memory with 1 GiB to spare.
+static int ensure_lplain(Plan &p, SizeSet &s, void *stream) {
+    if (s.d_la) return LJSDE_OK;
+    if (!s.d_lgroups) {
+        const std::vector<LGroup> order = lplain_groups(s);
+        LGroup *d = nullptr;
+        int st = dev_alloc((void **)&d, order.size() * sizeof(LGroup));
+        if (st) return st;
+        const hipError_t e = hipMemcpy(d, order.data(), order.size() * sizeof(LGroup), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return fail(LJSDE_EHIP, "L-JSDE group upload: %s", hipGetErrorString(e));
+        }
+        s.d_lgroups = d;
+        s.n_lgroups = (int)order.size();
+    }
+    const size_t abytes = lplain_a_bytes(p.Ws, s.n_classes()), xbytes = lplain_aux_bytes(p.Ws, s.n_classes());
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    if (abytes + xbytes + (1ull << 30) > free_b)
+        return fail(LJSDE_ENOMEM, "plain L-JSDE needs %.1f GiB of basis responses for %d classes, %.1f GiB free",
+                    (abytes + xbytes) / 1073741824.0, s.n_classes(), free_b / 1073741824.0);
+    void *a = nullptr, *x = nullptr;
+    int st = dev_alloc(&a, abytes);
+    if (st) return st;
+    st = dev_alloc(&x, xbytes);
+    if (st) {
+        (void)hipFree(a);
+        return st;
+    }
+    const int e = launch_lplain_build(make_params(p), s.d_tables, s.n_classes(), p.Ws, a, x, stream);
+    if (e) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        (void)hipFree(a);
+        (void)hipFree(x);
+        return fail(LJSDE_EHIP, "L-JSDE basis build: %s", hipGetErrorString((hipError_t)e));
+    }
+    s.d_la = a;
+    s.d_laux = x;
+    return LJSDE_OK;
+}
+
 static int reconstruct_impl(const void *y, int Ms, int Ns, int id, void *out, int16_t *sel, void *stream) {
     std::lock_guard<std::mutex> lk(g_mu);
     Plan *p = nullptr;
@@ -1171,7 +1262,11 @@ static int reconstruct_impl(const void *y, int Ms, int Ns, int id, void *out, in
     KParams k = make_params(*p);
     KJob j = make_job(*p, *s, y, out, sel, 0);
     int e = 0;
-    if (p->flags & LJSDE_DENSE_C) {
+    if (p->flags & LJSDE_PLAIN_L) {
+        st = ensure_lplain(*p, *s, stream);
+        if (st) return st;
+        e = launch_lplain(k, j, s->d_la, s->d_laux, s->d_lgroups, s->n_lgroups, p->Ws, stream);
+    } else if (p->flags & LJSDE_DENSE_C) {
         st = ensure_dense(*p, *s, stream);
         if (st) return st;
         e = launch_dense(k, j, s->d_dense, s->d_order, s->order_len, p->Ws, !p->fp64(), stream);
@@ -1287,6 +1382,9 @@ int ljsde_release(int pattern_id) {
         if (s.d_colcls) (void)hipFree(s.d_colcls);
         if (s.d_dense) (void)hipFree(s.d_dense);
         if (s.d_order) (void)hipFree(s.d_order);
+        if (s.d_la) (void)hipFree(s.d_la);
+        if (s.d_laux) (void)hipFree(s.d_laux);
+        if (s.d_lgroups) (void)hipFree(s.d_lgroups);
     }
     if (p->d_consts) (void)hipFree(p->d_consts);
     g_plans[pattern_id].reset();

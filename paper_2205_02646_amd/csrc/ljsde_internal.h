@@ -13,6 +13,7 @@ struct DevConsts {
     const double *dft;  // [Ws][2] exp(-i 2 pi k / Ws), k < Ws
     const double *H;    // [W*W][4][2] H_o(sigma, rho): response of the pixel of code o
                         // (its shape's quadrants) to the basis function (sigma, rho)
+    const double *q;    // [W*W]   frequency weight q of eqs. (10)-(11)
 };
 
 // KParams::shape of a plan with general per-pixel quadrant weights (Sec. II,
@@ -97,5 +98,24 @@ int launch_dense_c_build(const KParams &p, const unsigned char *tables, int n_cl
 int launch_dense(const KParams &p, const KJob &job, const void *C, const int *order, int order_len, int ws,
                  bool f32io, void *stream);
 size_t mixed_lds_bytes(int ws, int nw);
+
+// Plain L-JSDE (ljsde_lplain.hip): up to LGROUP windows of one class per
+// workgroup. `count` 0 marks an idle workgroup.
+constexpr int LGROUP = 16;
+struct LGroup {
+    int cls;
+    int count;
+    int win[LGROUP];  // window index inside the job, row-major block order
+};
+// Bytes of the basis responses a of n classes ([cls][W^2/16][(W/2)^2][16] complex)
+// and of their normalisers ([cls][2][W^2]: q/D, 1/D).
+size_t lplain_a_bytes(int ws, int n_classes);
+size_t lplain_aux_bytes(int ws, int n_classes);
+// Builds a (eq. (10): a_m(f) = sum A_m(eta, gamma) Phi(eta, gamma, f)) and, from it, D
+// of eq. (10) with q/D and 1/D for every class of a size set.
+int launch_lplain_build(const KParams &p, const unsigned char *tables, int n_classes, int ws, void *a, void *aux,
+                        void *stream);
+int launch_lplain(const KParams &p, const KJob &job, const void *a, const void *aux, const LGroup *groups,
+                  int ngroups, int ws, void *stream);
 
 }  // namespace ljsde

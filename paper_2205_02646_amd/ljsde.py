@@ -37,6 +37,7 @@ STATE_FP32 = 16
 DENSE_C = 32
 WEIGHTS = 64  # reported by plan_info for plans of plan_weights
 INPUT_F64 = 128  # FP32 plans: double measurements (float output)
+PLAIN_L = 4096  # FP64 plans: plain L-JSDE (residual in the measurement domain, eq. (10) every iteration)
 
 _NAMES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOMEM: "ENOMEM", EHIP: "EHIP", EBADID: "EBADID"}
 
@@ -106,35 +107,40 @@ def version() -> int:
 
 def plan(pattern, window: int = 32, block: int = 4, iters: int = 100, rho: float = 0.7,
          gamma: float = 0.5, fp64: bool = False, splitbf16: bool = False, q_ones: bool = False,
-         state_fp32: bool = False, shape: int = 0, dense_c: bool = False, input_f64: bool = False) -> int:
+         state_fp32: bool = False, shape: int = 0, dense_c: bool = False, input_f64: bool = False,
+         plain_l: bool = False) -> int:
     """Register a plan for a pattern tile of quadrant codes; returns its id.
     ``shape`` is the pixel-shape mask (0 or SHAPE_THREE_QUARTER: L-shaped
     pixels; SHAPE_QUARTER: one transparent quadrant per pixel). ``dense_c``
     selects the dense form (FP64 arithmetic; float32 I/O for FP32 plans): per
     class the full C of eq. (14) in device memory, R as the loop state.
     ``input_f64``: an FP32 plan that takes float64 measurements (the output
-    stays float32)."""
+    stays float32). ``plain_l`` (with ``fp64``): plain L-JSDE, the residual
+    kept in the measurement domain and eq. (10) evaluated densely."""
     pat = np.ascontiguousarray(np.asarray(pattern, dtype=np.uint8))
     if pat.ndim != 2:
         raise ValueError("pattern must be 2-D")
     flags = ((FP64 if fp64 else FP32) | (DFT_SPLITBF16 if splitbf16 else 0) | (Q_ONES if q_ones else 0)
              | (STATE_FP32 if state_fp32 else 0) | (DENSE_C if dense_c else 0) | SHAPE(shape)
-             | (INPUT_F64 if input_f64 else 0))
+             | (INPUT_F64 if input_f64 else 0) | (PLAIN_L if plain_l else 0))
     return _check(lib().ljsde_plan(pat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), pat.shape[0],
                                    pat.shape[1], window, block, iters, rho, gamma, flags))
 
 
 def plan_weights(weights, window: int = 32, block: int = 4, iters: int = 100, rho: float = 0.7,
-                 gamma: float = 0.5, q_ones: bool = False, fp64: bool = True, input_f64: bool = False) -> int:
+                 gamma: float = 0.5, q_ones: bool = False, fp64: bool = True, input_f64: bool = False,
+                 plain_l: bool = False) -> int:
     """Register a plan for a general layout: ``weights`` is a [rows, cols, 4]
     tile of per-pixel quadrant weights (quadrant 2a + b of the footprint).
     Runs on the dense form in FP64; ``fp64=False`` takes float32
     measurements and returns float32 images (float64 measurements with
-    ``input_f64``)."""
+    ``input_f64``). ``plain_l``: plain L-JSDE instead of the dense form
+    (FP64 only)."""
     wt = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
     if wt.ndim != 3 or wt.shape[2] != 4:
         raise ValueError("weights must be a [rows, cols, 4] tile")
-    flags = (FP64 if fp64 else FP32) | DENSE_C | (Q_ONES if q_ones else 0) | (INPUT_F64 if input_f64 else 0)
+    flags = ((FP64 if fp64 else FP32) | (PLAIN_L if plain_l else DENSE_C) | (Q_ONES if q_ones else 0)
+             | (INPUT_F64 if input_f64 else 0))
     return _check(lib().ljsde_plan_weights(wt.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), wt.shape[0],
                                            wt.shape[1], window, block, iters, rho, gamma, flags))
 

@@ -464,3 +464,24 @@ def test_empty_batch_is_refused():
     assert ljsde.lib().ljsde_reconstruct_batch(None, 0, None) == ljsde.EINVAL
     assert ljsde.lib().ljsde_autotune(None, 0, None) == ljsde.EINVAL
     assert "empty" in ljsde.last_error()
+
+
+def test_plain_l_flag_validation():
+    """LJSDE_PLAIN_L: FP64 plans only, not with the dense form; it lets two-
+    and four-quadrant masks and general layouts run without LJSDE_DENSE_C."""
+    assert ljsde.plan(TILE, iters=5, fp64=True, plain_l=True) >= 0
+    with pytest.raises(ljsde.LjsdeError) as e:
+        ljsde.plan(TILE, iters=5, fp64=False, plain_l=True)
+    assert e.value.code == ljsde.EINVAL
+    with pytest.raises(ljsde.LjsdeError) as e:
+        ljsde.plan(TILE, iters=5, fp64=True, plain_l=True, dense_c=True)
+    assert e.value.code == ljsde.EINVAL
+    pid = ljsde.plan(TILE, iters=5, fp64=True, plain_l=True, shape=0x3)  # half pixels
+    assert ljsde.plan_info(pid)["flags"] & ljsde.WEIGHTS
+    assert ljsde.plan_info(pid)["flags"] & ljsde.PLAIN_L
+    wt = random_weights(2, 2, seed=1)
+    pw = ljsde.plan_weights(wt, iters=5, plain_l=True)
+    assert ljsde.plan_info(pw)["flags"] & ljsde.PLAIN_L
+    with pytest.raises(ljsde.LjsdeError) as e:
+        ljsde.plan_weights(wt, iters=5, plain_l=True, fp64=False)
+    assert e.value.code == ljsde.EINVAL

@@ -1,0 +1,134 @@
+"""GPU parity of plain L-JSDE (plans with LJSDE_PLAIN_L): the residual kept in
+the measurement domain and the numerator of eq. (10) evaluated as a dense
+product every iteration, against the oracle's literal L-JSDE form
+(``ljsde_window``: residual in the measurement domain, eq. (10) as a dense
+matrix-vector product). FP64 bar: max-abs <= 1e-9 and equal selection
+sequences, on ragged and non-recurrent images, W = 16 and 32, B = 4 and 8,
+quarter sampling, general layouts, q = 1, other rho and gamma, and the energy
+floor. The larger cases compare with the oracle's recurrent form, which the
+oracle's pins hold equal to the literal form (RL == L), or with the GPU's
+recurrent FP64 path on every window."""
+import numpy as np
+import pytest
+
+from oracle import ljsde_oracle as O
+from synth import QUARTER, THREE_QUARTER, make_case, random_weights, sense_weights, synthetic_image
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_02646_amd import ljsde
+    ljsde.lib()
+    return ljsde
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+
+
+CASES = {
+    # name: (rows, cols, pattern, W, B, iters, rho, gamma, q_ones, seed, shape, oracle form)
+    "w32b4_ragged": (48, 40, 4, 32, 4, 30, 0.7, 0.5, False, 5, THREE_QUARTER, "L"),
+    "w16b8": (40, 56, (3, 5), 16, 8, 30, 0.7, 0.5, False, 7, THREE_QUARTER, "L"),
+    "w16b4_q_ones": (40, 40, 4, 16, 4, 25, 0.5, 1.5, True, 8, THREE_QUARTER, "L"),
+    "quarter_w32b4": (40, 48, 4, 32, 4, 25, 0.7, 0.5, False, 11, QUARTER, "L"),
+    "one_block": (4, 4, None, 32, 4, 20, 0.7, 0.5, False, 14, THREE_QUARTER, "L"),
+    # the non-recurrent 64 x 64 image of the L-JSDE workload, 100 iterations
+    "nonrecurrent_64": (64, 64, None, 32, 4, 100, 0.7, 0.5, False, 0, THREE_QUARTER, "RL"),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_plain_l_matches_oracle(L, name):
+    rows, cols, pattern, W, B, iters, rho, gamma, q_ones, seed, shape, form = CASES[name]
+    c = make_case(rows, cols, pattern, seed=seed, shape=shape)
+    ref, tr = O.reconstruct(c["y"], c["tile"], W=W, B=B, iters=iters, rho=rho, gamma=gamma, form=form,
+                            q_mode="ones" if q_ones else "fsr", shape=shape, traces=True)
+    pid = L.plan(c["tile"], window=W, block=B, iters=iters, rho=rho, gamma=gamma, q_ones=q_ones, fp64=True,
+                 plain_l=True, shape=0 if shape == THREE_QUARTER else shape)
+    print(f"plain L-JSDE case {name}", flush=True)
+    out, sel = L.reconstruct_diag(_dev(c["y"]), pid)
+    out, sel = out.cpu().numpy(), sel.cpu().numpy()
+    err = float(np.max(np.abs(out - ref)))
+    print(f"{name}: plain L-JSDE max-abs {err:.3e} (oracle form {form})")
+    assert err <= FP64_TOL
+    nbj = out.shape[1] // B
+    for w in range(sel.shape[0]):
+        assert list(sel[w]) == tr[divmod(w, nbj)].picks, w
+    # the selection-free call gives the same output
+    out2 = L.reconstruct(_dev(c["y"]), pid).cpu().numpy()
+    assert np.array_equal(out, out2)
+    L.release(pid)
+
+
+@pytest.mark.parametrize("W,B", [(32, 4), (16, 8)])
+def test_plain_l_general_layout_matches_oracle(L, W, B):
+    wt = random_weights(4, 4, seed=3)
+    _, obs = synthetic_image(48, 40, seed=9)
+    y = sense_weights(obs, wt)
+    ref, tr = O.reconstruct(y, None, W=W, B=B, iters=25, weights=wt, form="L", traces=True)
+    pid = L.plan_weights(wt, window=W, block=B, iters=25, plain_l=True)
+    out, sel = L.reconstruct_diag(_dev(y), pid)
+    out, sel = out.cpu().numpy(), sel.cpu().numpy()
+    err = float(np.max(np.abs(out - ref)))
+    print(f"general layout W={W} B={B}: plain L-JSDE max-abs {err:.3e}")
+    assert err <= FP64_TOL
+    nbj = out.shape[1] // B
+    for w in range(sel.shape[0]):
+        assert list(sel[w]) == tr[divmod(w, nbj)].picks, w
+    L.release(pid)
+
+
+def test_plain_l_energy_floor_matches_a_shorter_oracle_run(L):
+    """With an energy floor a window stops once E <= tau E(0) (eq. (8),
+    closed form in FP64); every window's output equals the oracle's run of
+    as many iterations as the window made, and the selections after its stop
+    are -1."""
+    c = make_case(40, 48, 4, seed=12)
+    pid = L.plan(c["tile"], iters=40, fp64=True, plain_l=True)
+    L.set_energy_floor(pid, 0.02)
+    out, sel = L.reconstruct_diag(_dev(c["y"]), pid)
+    out, sel = out.cpu().numpy(), sel.cpu().numpy()
+    ref, tr = O.reconstruct(c["y"], c["tile"], W=32, B=4, iters=40, form="RL", traces=True)
+    nbj = out.shape[1] // 4
+    stopped = 0
+    for w in range(sel.shape[0]):
+        n = int(np.sum(sel[w] >= 0))
+        assert (sel[w][n:] == -1).all()
+        picks = tr[divmod(w, nbj)].picks
+        assert list(sel[w][:n]) == picks[:n], w
+        bi, bj = divmod(w, nbj)
+        blk = np.s_[4 * bi:4 * bi + 4, 4 * bj:4 * bj + 4]
+        if n < 40:
+            stopped += 1
+            short = O.reconstruct(c["y"], c["tile"], W=32, B=4, iters=n, form="RL", blocks=[(bi, bj)])
+            assert np.max(np.abs(out[blk] - short[blk])) <= FP64_TOL
+        else:
+            assert np.max(np.abs(out[blk] - ref[blk])) <= FP64_TOL
+    assert stopped > 0
+    L.release(pid)
+
+
+def test_plain_l_equals_recurrent_fp64_on_every_window(L):
+    """A 128 x 128 frame (1024 windows) with a recurrent 4 x 4 tile: plain
+    L-JSDE and the recurrent FP64 path give equal selections on every window
+    and outputs within 1e-9 (Sec. V: the recurrent form reaches the L-JSDE
+    result)."""
+    c = make_case(128, 128, 4, seed=2)
+    pl = L.plan(c["tile"], iters=100, fp64=True, plain_l=True)
+    pr = L.plan(c["tile"], iters=100, fp64=True)
+    ol, sl = L.reconstruct_diag(_dev(c["y"]), pl)
+    orr, sr = L.reconstruct_diag(_dev(c["y"]), pr)
+    err = float(torch.max(torch.abs(ol - orr)))
+    print(f"128x128: plain L vs recurrent FP64 max-abs {err:.3e}")
+    assert err <= FP64_TOL
+    assert torch.equal(sl, sr)
+    L.release(pl)
+    L.release(pr)

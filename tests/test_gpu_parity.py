@@ -461,7 +461,7 @@ def test_energy_floor_change_reaches_the_batched_path(L):
     c = make_case(40, 40, 4, seed=77)
     pid = L.plan(c["tile"], iters=60, input_f64=True)
     y = _dev(c["y"], np.float64)
-    out = torch.empty((80, 80), dtype=torch.float32, device="cuda:0")
+    out = torch.empty((40, 40), dtype=torch.float32, device="cuda:0")
     L.reconstruct_batch([(y, pid, out)])
     no_floor = out.clone()
     L.set_energy_floor(pid, 0.02)
