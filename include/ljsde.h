@@ -231,6 +231,36 @@ typedef struct {
 int ljsde_reconstruct_batch(const ljsde_job *jobs, int n_jobs, void *stream);
 
 /*
+ * ljsde_reconstruct_noalloc -- ljsde_reconstruct for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation). It runs the same persistent FP32 kernel
+ * as ljsde_reconstruct with a batch of one, with the same results; its work
+ * memory (work counters, the job and the list of window groups) is a static
+ * device array of the library, one per GPU, held until the process ends.
+ *  measurements, sensor_rows, sensor_cols, pattern_id, out, stream
+ *            as for ljsde_reconstruct. FP32 plans of the factorised form
+ *            only (LJSDE_FP64, LJSDE_DENSE_C and LJSDE_STATE_FP32 plans ->
+ *            LJSDE_EUNSUPPORTED).
+ * Precondition: the plan has already reconstructed an image of this sensor
+ * size on this device (ljsde_reconstruct, ljsde_reconstruct_batch or
+ * ljsde_reconstruct_diag build and upload its class tables); otherwise
+ * LJSDE_EINVAL, and nothing runs.
+ * Limit: the work list holds at most 262144 groups (6 MiB). A group holds up
+ * to 4 windows of one local measurement matrix (4 by default, or the width
+ * ljsde_autotune chose for that shape: 1, 2 or 4), so images of more than
+ * 1048576 target blocks (e.g. beyond 4096 x 4096 output pixels at B = 4), and
+ * smaller ones whose list exceeds the limit, are LJSDE_EINVAL.
+ * The call makes no device allocation or free. It builds its host-side work
+ * list once per plan, image size and group width (host memory, kept with the
+ * plan) and uploads it only when that changes since the device's last call.
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (other streams or threads) race and
+ * must be serialised by the caller.
+ */
+int ljsde_reconstruct_noalloc(const void *measurements, int sensor_rows, int sensor_cols,
+                              int pattern_id, void *out, void *stream);
+
+/*
  * ljsde_autotune -- time the launch variants of the persistent kernel
  * (windows per workgroup, work-chunk size, resident workgroups per compute
  * unit) on this batch and keep the

@@ -99,6 +99,12 @@ struct SizeSet {
     void *d_laux = nullptr;    // plain L-JSDE: q/D and 1/D of every class
     LGroup *d_lgroups = nullptr;  // plain L-JSDE: window groups in launch order
     int n_lgroups = 0;
+    // host work lists of the allocation-free entry point, per group width
+    struct GroupList {
+        std::vector<WinGroup> groups;
+        int ranges[XCD_RANGES + 1];
+    };
+    std::map<int, GroupList> noalloc_lists;
 };
 
 struct Plan {
@@ -942,7 +948,7 @@ using namespace ljsde;
 
 extern "C" {
 
-int ljsde_version(void) { return 10300; }  // 1.3: LJSDE_PLAIN_L (1.2: LJSDE_INPUT_F64; 1.1: ljsde_plan_weights, every pixel-shape mask)
+int ljsde_version(void) { return 10300; }  // 1.3: LJSDE_PLAIN_L, ljsde_reconstruct_noalloc (1.2: LJSDE_INPUT_F64; 1.1: ljsde_plan_weights, every pixel-shape mask)
 
 int ljsde_plan_info(int pattern_id, int *window, int *block, int *iters, unsigned *flags) {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -1297,6 +1303,76 @@ int ljsde_reconstruct_diag(const void *measurements, int sensor_rows, int sensor
 int ljsde_reconstruct_batch(const ljsde_job *jobs, int n_jobs, void *stream) {
     std::lock_guard<std::mutex> lk(g_mu);
     return run_batch(jobs, n_jobs, stream);
+}
+
+// The work memory of this call is the per-GPU device array of
+// ljsde_mixed.hip, which keeps the work list of its last call: the list is
+// uploaded again only when the plan, the image size or the group width
+// changes. The host copy of a list stays with the plan's size set.
+int ljsde_reconstruct_noalloc(const void *measurements, int sensor_rows, int sensor_cols, int pattern_id,
+                              void *out, void *stream) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan *p = nullptr;
+    int st = get_plan(pattern_id, &p);
+    if (st) return st;
+    if (p->fp64() || (p->flags & (LJSDE_DENSE_C | LJSDE_STATE_FP32)))
+        return fail(LJSDE_EUNSUPPORTED, "ljsde_reconstruct_noalloc needs an FP32 plan of the factorised form "
+                                        "(not LJSDE_FP64, LJSDE_DENSE_C or LJSDE_STATE_FP32)");
+    if (!measurements || !out) return fail(LJSDE_EINVAL, "null device pointer");
+    st = check_size(*p, sensor_rows, sensor_cols);
+    if (st) return st;
+    const long long nwin = (long long)(2 * sensor_rows / p->B) * (2 * sensor_cols / p->B);
+    if (nwin > 4LL * NOALLOC_MAX_GROUPS)
+        return fail(LJSDE_EINVAL, "%dx%d sensor: %lld windows exceed the work memory of ljsde_reconstruct_noalloc "
+                                  "(%d groups of at most 4 windows)", sensor_rows, sensor_cols, nwin,
+                    NOALLOC_MAX_GROUPS);
+    auto it = p->sizes.find(std::make_pair(sensor_rows, sensor_cols));
+    if (it == p->sizes.end() || !it->second->d_tables)
+        return fail(LJSDE_EINVAL, "plan %d has no device tables for a %dx%d sensor: reconstruct one image of "
+                                  "that size with the plan first (ljsde_reconstruct or a batch builds them)",
+                    pattern_id, sensor_rows, sensor_cols);
+    SizeSet &s = *it->second;
+    int dev = 0;
+    st = current_device(&dev);
+    if (st) return st;
+    if (s.device != dev)
+        return fail(LJSDE_EUNSUPPORTED, "plan tables live on device %d, current device is %d", s.device, dev);
+    if ((st = check_device_buffer(measurements, "measurements", -1)) || (st = check_device_buffer(out, "out", -1)))
+        return st;
+    // the launch variant the autotuner chose for this shape, else the default
+    TuneChoice c;
+    load_tune_cache();
+    auto t = g_tuned.find(tune_key(*p, false, nwin, s.n_classes()));
+    if (t != g_tuned.end()) c = t->second;
+    const int nw = c.waves_per_block;
+    SizeSet::GroupList &gl = s.noalloc_lists[nw];
+    if (gl.groups.empty()) make_group_list({&s}, nw, gl.groups, gl.ranges);
+    if (gl.groups.size() > (size_t)NOALLOC_MAX_GROUPS)
+        return fail(LJSDE_EINVAL, "%dx%d sensor: %zu window groups exceed the work memory of "
+                                  "ljsde_reconstruct_noalloc (%d groups)", sensor_rows, sensor_cols,
+                    gl.groups.size(), NOALLOC_MAX_GROUPS);
+    int grid = 0;
+    st = grid_for_shape(p->Ws, false, c, &grid);
+    if (st) return st;
+    unsigned char *scr = nullptr;
+    int e = noalloc_scratch(dev, &scr);
+    if (e) return fail(LJSDE_EHIP, "work memory address: %s", hipGetErrorString((hipError_t)e));
+    // what the device array holds: (plan, sensor rows, sensor cols, group width) per device
+    static int loaded[64][4];
+    static bool valid[64];
+    const int key[4] = {pattern_id, sensor_rows, sensor_cols, nw};
+    const bool upload = !(dev < 64 && valid[dev] && std::equal(key, key + 4, loaded[dev]));
+    const KParams k = make_params(*p);
+    const KJob j = make_job(*p, s, measurements, out, nullptr, 0);
+    if (dev < 64) valid[dev] = false;
+    e = launch_mixed_noalloc(k, j, gl.groups.data(), (int)gl.groups.size(), gl.ranges, upload, p->Ws, nw, grid,
+                             scr, stream);
+    if (e) return fail(LJSDE_EHIP, "allocation-free launch: %s", hipGetErrorString((hipError_t)e));
+    if (dev < 64) {
+        std::copy(key, key + 4, loaded[dev]);
+        valid[dev] = true;
+    }
+    return ok();
 }
 
 int ljsde_autotune(const ljsde_job *jobs, int n_jobs, void *stream) {

@@ -118,4 +118,23 @@ int launch_lplain_build(const KParams &p, const unsigned char *tables, int n_cla
 int launch_lplain(const KParams &p, const KJob &job, const void *a, const void *aux, const LGroup *groups,
                   int ngroups, int ws, void *stream);
 
+// Allocation-free single-image launch of the persistent FP32 kernel. Its work
+// memory (counters, group ranges, the job and the window groups) is a
+// file-scope device array in ljsde_mixed.hip, one copy per GPU, of
+// NOALLOC_BYTES; the work list holds at most NOALLOC_MAX_GROUPS groups.
+constexpr int NOALLOC_MAX_GROUPS = 1 << 18;
+constexpr size_t NOALLOC_OFF_RANGES = 256;   // int [XCD_RANGES + 1]
+constexpr size_t NOALLOC_OFF_JOB = 512;      // KJob
+constexpr size_t NOALLOC_OFF_GROUPS = 1024;  // WinGroup [NOALLOC_MAX_GROUPS]
+constexpr size_t NOALLOC_BYTES = NOALLOC_OFF_GROUPS + (size_t)NOALLOC_MAX_GROUPS * sizeof(WinGroup);
+// Device address of the array on device `dev` (the current device), looked
+// up once per device. Returns a hipError_t value.
+int noalloc_scratch(int dev, unsigned char **ptr);
+// With `upload`, copies the host work list (which must outlive the copy) into
+// the array; then one fill kernel writes the job, the ranges and zeroed
+// counters, and the persistent kernel runs on them. Returns a hipError_t value.
+int launch_mixed_noalloc(const KParams &p, const KJob &job, const WinGroup *host_groups, int ngroups,
+                         const int *ranges, bool upload, int ws, int nw, int grid, unsigned char *scr,
+                         void *stream);
+
 }  // namespace ljsde

@@ -499,4 +499,65 @@ int mixed_blocks_per_cu(int ws, int nw, int *blocks) {
     return nw == 1 ? occ_mp<8, 1>(blocks) : nw == 2 ? occ_mp<8, 2>(blocks) : occ_mp<8, 4>(blocks);
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free single-image launch
+// ---------------------------------------------------------------------------
+
+// Work memory of the allocation-free launch: COUNTERS work counters at 0, the
+// group ranges at NOALLOC_OFF_RANGES, the job at NOALLOC_OFF_JOB and the work
+// list at NOALLOC_OFF_GROUPS. Each GPU holds its own copy until the process
+// ends; host code reaches it only through the address noalloc_scratch returns.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+static_assert(sizeof(KJob) <= NOALLOC_OFF_GROUPS - NOALLOC_OFF_JOB, "job slot too small");
+static_assert((XCD_RANGES + 1) * sizeof(int) <= NOALLOC_OFF_JOB - NOALLOC_OFF_RANGES, "range slot too small");
+static_assert(COUNTERS * sizeof(unsigned int) <= NOALLOC_OFF_RANGES, "counter slot too small");
+
+struct NoallocRanges {
+    int r[XCD_RANGES + 1];
+};
+
+// Writes the job, the group ranges and zeroed work counters (one wavefront).
+__global__ void noalloc_setup_kernel(KJob job, NoallocRanges rg, unsigned char *scr) {
+    const int t = threadIdx.x;
+    if (t < COUNTERS) ((unsigned int *)scr)[t] = 0u;
+    if (t <= XCD_RANGES) ((int *)(scr + NOALLOC_OFF_RANGES))[t] = rg.r[t];
+    if (t == 0) *(KJob *)(scr + NOALLOC_OFF_JOB) = job;
+}
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static unsigned char *g_scratch_addr[NOALLOC_MAX_DEVICES];
+
+// The caller holds the library lock, so the table needs no lock of its own.
+int noalloc_scratch(int dev, unsigned char **ptr) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return (int)hipErrorInvalidDevice;
+    if (!g_scratch_addr[dev]) {
+        void *a = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        g_scratch_addr[dev] = (unsigned char *)a;
+    }
+    *ptr = g_scratch_addr[dev];
+    return 0;
+}
+
+int launch_mixed_noalloc(const KParams &p, const KJob &job, const WinGroup *host_groups, int ngroups,
+                         const int *ranges, bool upload, int ws, int nw, int grid, unsigned char *scr,
+                         void *stream) {
+    if (ngroups < 0 || ngroups > NOALLOC_MAX_GROUPS) return (int)hipErrorInvalidValue;
+    if (upload && ngroups > 0) {
+        const hipError_t e = hipMemcpyAsync(scr + NOALLOC_OFF_GROUPS, host_groups, sizeof(WinGroup) * ngroups,
+                                            hipMemcpyHostToDevice, (hipStream_t)stream);
+        if (e != hipSuccess) return (int)e;
+    }
+    NoallocRanges rg;
+    for (int r = 0; r <= XCD_RANGES; ++r) rg.r[r] = ranges[r];
+    noalloc_setup_kernel<<<dim3(1), dim3(64), 0, (hipStream_t)stream>>>(job, rg, scr);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+    return launch_mixed_persistent(p, (const KJob *)(scr + NOALLOC_OFF_JOB),
+                                   (const WinGroup *)(scr + NOALLOC_OFF_GROUPS),
+                                   (const int *)(scr + NOALLOC_OFF_RANGES), (unsigned int *)scr, ws, nw, grid,
+                                   stream);
+}
+
 }  // namespace ljsde

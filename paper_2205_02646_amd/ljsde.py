@@ -76,6 +76,7 @@ def lib():
     L.ljsde_reconstruct.argtypes = [vp, i, i, i, vp, vp]
     L.ljsde_reconstruct_diag.argtypes = [vp, i, i, i, vp, vp, vp]
     L.ljsde_reconstruct_batch.argtypes = [ctypes.POINTER(Job), i, vp]
+    L.ljsde_reconstruct_noalloc.argtypes = [vp, i, i, i, vp, vp]
     L.ljsde_autotune.argtypes = [ctypes.POINTER(Job), i, vp]
     L.ljsde_synchronize.argtypes = [vp]
     L.ljsde_release.argtypes = [i]
@@ -84,7 +85,7 @@ def lib():
     L.ljsde_class_tables.argtypes = [i, i, i, i, vp, vp, vp]
     L.ljsde_plan_info.argtypes = [i, vp, vp, vp, vp]
     for name in ("ljsde_plan", "ljsde_plan_weights", "ljsde_set_energy_floor", "ljsde_reconstruct", "ljsde_reconstruct_diag",
-                 "ljsde_reconstruct_batch", "ljsde_autotune", "ljsde_synchronize", "ljsde_release",
+                 "ljsde_reconstruct_batch", "ljsde_reconstruct_noalloc", "ljsde_autotune", "ljsde_synchronize", "ljsde_release",
                  "ljsde_class_count", "ljsde_class_tables", "ljsde_plan_info", "ljsde_version"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -216,6 +217,19 @@ def reconstruct_diag(y, pid: int, out=None, stream=None):
     sel = torch.empty((n_win, info["iters"]), dtype=torch.int16, device=y.device)
     out = reconstruct(y, pid, out=out, stream=stream, selections=sel)
     return out, sel
+
+
+def reconstruct_noalloc(y, pid: int, out, stream=None):
+    """As ``reconstruct`` for an FP32 plan of the factorised form, through the
+    entry point that allocates no device memory: ``out`` must be given, and
+    the plan must already have reconstructed an image of this size (which
+    built its tables)."""
+    ydt, odt = _dtypes(pid)
+    _as_input(y, ydt)
+    _check_out(y, out, odt)
+    R, C = y.shape
+    _check(lib().ljsde_reconstruct_noalloc(y.data_ptr(), R, C, pid, out.data_ptr(), _stream(stream)))
+    return out
 
 
 def plan_info(pid: int) -> dict:

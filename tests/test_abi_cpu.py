@@ -466,6 +466,31 @@ def test_empty_batch_is_refused():
     assert "empty" in ljsde.last_error()
 
 
+def test_noalloc_refusals_are_host_side():
+    """ljsde_reconstruct_noalloc refuses, before touching a device: plans
+    without the persistent FP32 kernel, images beyond its work memory, and
+    sizes whose class tables are not resident yet."""
+    lib = ljsde.lib()
+    fake_y, fake_out = ctypes.c_void_p(4096), ctypes.c_void_p(8192)  # never dereferenced: refused first
+    p64 = ljsde.plan(TILE, iters=5, fp64=True)
+    pd = ljsde.plan(TILE, iters=5, fp64=False, dense_c=True)
+    ps = ljsde.plan(TILE, iters=5, state_fp32=True)
+    for pid in (p64, pd, ps):
+        assert lib.ljsde_reconstruct_noalloc(fake_y, 16, 16, pid, fake_out, None) == ljsde.EUNSUPPORTED
+    p = ljsde.plan(TILE, iters=5)
+    assert lib.ljsde_reconstruct_noalloc(None, 16, 16, p, fake_out, None) == ljsde.EINVAL
+    assert lib.ljsde_reconstruct_noalloc(fake_y, 15, 16, p, fake_out, None) == ljsde.EINVAL  # odd side at B = 4
+    # 2100 x 2100 sensor pixels: 1050^2 target blocks > 262144 groups of 4
+    assert lib.ljsde_reconstruct_noalloc(fake_y, 2100, 2100, p, fake_out, None) == ljsde.EINVAL
+    assert "work memory" in ljsde.last_error()
+    # no reconstruction of this size yet: no device tables
+    assert lib.ljsde_reconstruct_noalloc(fake_y, 16, 16, p, fake_out, None) == ljsde.EINVAL
+    assert "tables" in ljsde.last_error()
+    assert lib.ljsde_reconstruct_noalloc(fake_y, 16, 16, 10 ** 6, fake_out, None) == ljsde.EBADID
+    for pid in (p64, pd, ps, p):
+        ljsde.release(pid)
+
+
 def test_plain_l_flag_validation():
     """LJSDE_PLAIN_L: FP64 plans only, not with the dense form; it lets two-
     and four-quadrant masks and general layouts run without LJSDE_DENSE_C."""
