@@ -580,8 +580,9 @@ def main():
     launch = None
     try:
         with open(tune_file) as fh:
-            launch = {k: {"waves_per_workgroup": v[0], "workgroups_per_cu_below_max": v[2],
-                          **({"knobs": v[3:]} if len(v) > 3 else {})}
+            launch = {k: {"waves_per_workgroup": v[0], "groups_per_claim": v[1], "workgroups_per_cu_below_max": v[2],
+                          **({"qd_twiddles": "registers" if v[3] else "lds",
+                              "window_dft": "valu" if v[4] else "mfma_f64_16x16x4"} if len(v) > 4 else {})}
                       for k, v in json.load(fh).items()}
     except (OSError, ValueError, IndexError):
         pass

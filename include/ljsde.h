@@ -261,12 +261,21 @@ int ljsde_reconstruct_noalloc(const void *measurements, int sensor_rows, int sen
                               int pattern_id, void *out, void *stream);
 
 /*
- * ljsde_autotune -- time the launch variants of the persistent kernel
- * (windows per workgroup, work-chunk size, resident workgroups per compute
- * unit) on this batch and keep the
- * fastest for later batch calls of the same shape class. Results are cached
- * in memory and, if LJSDE_TUNE_CACHE names a file, in that JSON file.
- * Synchronises `stream`. Outputs of the batch are overwritten.
+ * ljsde_autotune -- time the launch variants of the persistent kernel on this
+ * batch and keep the fastest for later batch calls of the same shape class:
+ * windows per workgroup (1, 2, 4), resident workgroups per compute unit (the
+ * maximum or one fewer), window groups taken per work claim (1, 2, 4), and,
+ * for W = 32 without split-BF16, the LDS layout (per-lane q/D and twiddles
+ * re-read from LDS every iteration, or held in registers) and the DFT tile
+ * shape (the window DFT on FP64 MFMA 16x16x4 tiles, or as FP64 VALU row and
+ * column passes, which sums in another order: outputs equal up to FP64
+ * rounding). The search is staged: the first two knobs, then the claim
+ * size, then the last two, each from the best so far. Results are cached in
+ * memory and, if LJSDE_TUNE_CACHE names a file, in that JSON file ("key" :
+ * [windows per workgroup, groups per claim, fewer workgroups, q/D in
+ * registers, VALU DFT]). Synchronises `stream`. Outputs of the batch are
+ * overwritten. For tests, LJSDE_VARIANT="nw,chunk,fewer,qreg,vdft" in the
+ * environment forces the variant of batch states created afterwards.
  */
 int ljsde_autotune(const ljsde_job *jobs, int n_jobs, void *stream);
 

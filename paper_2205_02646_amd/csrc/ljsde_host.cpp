@@ -556,9 +556,22 @@ KJob make_job(const Plan &p, const SizeSet &s, const void *y, void *out, int16_t
 // the latter, windows per work grab.
 struct TuneChoice {
     int waves_per_block = 4;
-    int chunk = 2;
+    int chunk = 2;         // FP32-state path: windows per grab; FP64-state path: groups per claim
     int fewer_blocks = 0;  // resident workgroups per CU below the occupancy maximum
+    int qreg = 0;          // FP64-state path: per-lane q/D and twiddles held in registers
+    int vdft = 0;          // FP64-state path: window DFT as VALU passes instead of FP64 MFMA
 };
+
+TuneChoice default_choice(bool state_fp32) { return state_fp32 ? TuneChoice{1, 2} : TuneChoice{4, 1, 0}; }
+
+MixedVariant mixed_variant(const TuneChoice &c) {
+    MixedVariant v;
+    v.nw = c.waves_per_block;
+    v.chunk = c.chunk;
+    v.qreg = c.qreg != 0;
+    v.vdft = c.vdft != 0;
+    return v;
+}
 
 struct BatchState {
     bool state_fp32 = false;            // all-FP32 variant (LJSDE_STATE_FP32)
@@ -617,7 +630,8 @@ void load_tune_cache() {
     std::ifstream f(path);
     if (!f) return;
     std::string line;
-    // one entry per line: "key" : [waves_per_block, chunk, fewer_blocks]
+    // one entry per line: "key" : [waves_per_block, chunk, fewer_blocks, qreg, vdft]
+    // (entries of three numbers: qreg = vdft = 0)
     while (std::getline(f, line)) {
         size_t a = line.find('"');
         if (a == std::string::npos) continue;
@@ -626,9 +640,12 @@ void load_tune_cache() {
         size_t l = line.find('[', b);
         if (l == std::string::npos || line.find(']', l) == std::string::npos) continue;
         TuneChoice c;
-        if (sscanf(line.c_str() + l + 1, "%d , %d , %d", &c.waves_per_block, &c.chunk, &c.fewer_blocks) == 3 &&
+        const int n = sscanf(line.c_str() + l + 1, "%d , %d , %d , %d , %d", &c.waves_per_block, &c.chunk,
+                             &c.fewer_blocks, &c.qreg, &c.vdft);
+        if ((n == 3 || n == 5) &&
             (c.waves_per_block == 1 || c.waves_per_block == 2 || c.waves_per_block == 4) && c.chunk >= 1 &&
-            c.chunk <= 64 && c.fewer_blocks >= 0 && c.fewer_blocks < 8)
+            c.chunk <= 64 && c.fewer_blocks >= 0 && c.fewer_blocks < 8 && (c.qreg == 0 || c.qreg == 1) &&
+            (c.vdft == 0 || c.vdft == 1))
             g_tuned[line.substr(a + 1, b - a - 1)] = c;
     }
 }
@@ -646,7 +663,7 @@ void save_tune_cache() {
         size_t i = 0;
         for (auto &kv : g_tuned) {
             f << "  \"" << kv.first << "\" : [" << kv.second.waves_per_block << ", " << kv.second.chunk << ", "
-              << kv.second.fewer_blocks << "]"
+              << kv.second.fewer_blocks << ", " << kv.second.qreg << ", " << kv.second.vdft << "]"
               << (++i < g_tuned.size() ? "," : "") << "\n";
         }
         f << "}\n";
@@ -659,12 +676,25 @@ void save_tune_cache() {
     if (std::rename(tmp.c_str(), path) != 0) std::remove(tmp.c_str());
 }
 
+// Test hook: LJSDE_VARIANT="nw,chunk,fewer,qreg,vdft" forces the launch
+// variant of batch states created afterwards (ignored when malformed).
+void forced_variant(TuneChoice *c) {
+    const char *v = getenv("LJSDE_VARIANT");
+    if (!v) return;
+    TuneChoice f;
+    if (sscanf(v, "%d,%d,%d,%d,%d", &f.waves_per_block, &f.chunk, &f.fewer_blocks, &f.qreg, &f.vdft) == 5 &&
+        (f.waves_per_block == 1 || f.waves_per_block == 2 || f.waves_per_block == 4) && f.chunk >= 1 &&
+        f.chunk <= 64 && f.fewer_blocks >= 0 && f.fewer_blocks < 8 && (f.qreg == 0 || f.qreg == 1) &&
+        (f.vdft == 0 || f.vdft == 1))
+        *c = f;
+}
+
 int grid_for_shape(int ws, bool state_fp32, const TuneChoice &c, int *grid) {
     int dev = 0, ncu = 0, blocks = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     const int e = state_fp32 ? persistent_blocks_per_cu(ws, c.waves_per_block, &blocks)
-                             : mixed_blocks_per_cu(ws, c.waves_per_block, &blocks);
+                             : mixed_blocks_per_cu(ws, mixed_variant(c), &blocks);
     if (e != 0 || blocks <= 0) return fail(LJSDE_EHIP, "occupancy query failed (%d)", e);
     // a grid below full occupancy can finish a batch in whole rounds
     *grid = ncu * std::max(1, blocks - c.fewer_blocks);
@@ -818,7 +848,7 @@ int prepare_batch(const ljsde_job *jobs, int n, void *stream, BatchState **out) 
         b->ws = p0->Ws;
         b->device = dev;
         b->tune_key = tune_key(*p0, sf32, total, n_classes);
-        if (sf32) b->choice = TuneChoice{1, 2};
+        b->choice = default_choice(sf32);
         st = dev_alloc((void **)&b->d_jobs, sizeof(KJob) * n);
         if (st) return st;
         st = dev_alloc((void **)&b->d_counter, sizeof(unsigned int) * COUNTERS);
@@ -826,6 +856,7 @@ int prepare_batch(const ljsde_job *jobs, int n, void *stream, BatchState **out) 
         load_tune_cache();
         auto t = g_tuned.find(b->tune_key);
         if (t != g_tuned.end()) b->choice = t->second;
+        forced_variant(&b->choice);
         st = grid_for(*b, b->choice, &b->grid);
         if (st) return st;
         if (!sf32) {
@@ -867,7 +898,7 @@ int launch_batch_eager(BatchState &b, const TuneChoice &c, int grid, void *strea
                                   c.waves_per_block, c.chunk, grid, stream);
     else
         e = launch_mixed_persistent(b.params, b.d_jobs, b.d_groups, b.d_ranges, b.d_counter, b.ws,
-                                    c.waves_per_block, grid, stream);
+                                    mixed_variant(c), grid, stream);
     if (e) return fail(LJSDE_EHIP, "persistent launch: %s", hipGetErrorString((hipError_t)e));
     return LJSDE_OK;
 }
@@ -1340,10 +1371,11 @@ int ljsde_reconstruct_noalloc(const void *measurements, int sensor_rows, int sen
     if ((st = check_device_buffer(measurements, "measurements", -1)) || (st = check_device_buffer(out, "out", -1)))
         return st;
     // the launch variant the autotuner chose for this shape, else the default
-    TuneChoice c;
+    TuneChoice c = default_choice(false);
     load_tune_cache();
     auto t = g_tuned.find(tune_key(*p, false, nwin, s.n_classes()));
     if (t != g_tuned.end()) c = t->second;
+    forced_variant(&c);
     const int nw = c.waves_per_block;
     SizeSet::GroupList &gl = s.noalloc_lists[nw];
     if (gl.groups.empty()) make_group_list({&s}, nw, gl.groups, gl.ranges);
@@ -1365,8 +1397,8 @@ int ljsde_reconstruct_noalloc(const void *measurements, int sensor_rows, int sen
     const KParams k = make_params(*p);
     const KJob j = make_job(*p, s, measurements, out, nullptr, 0);
     if (dev < 64) valid[dev] = false;
-    e = launch_mixed_noalloc(k, j, gl.groups.data(), (int)gl.groups.size(), gl.ranges, upload, p->Ws, nw, grid,
-                             scr, stream);
+    e = launch_mixed_noalloc(k, j, gl.groups.data(), (int)gl.groups.size(), gl.ranges, upload, p->Ws,
+                             mixed_variant(c), grid, scr, stream);
     if (e) return fail(LJSDE_EHIP, "allocation-free launch: %s", hipGetErrorString((hipError_t)e));
     if (dev < 64) {
         std::copy(key, key + 4, loaded[dev]);
@@ -1380,11 +1412,6 @@ int ljsde_autotune(const ljsde_job *jobs, int n_jobs, void *stream) {
     BatchState *b = nullptr;
     int st = prepare_batch(jobs, n_jobs, stream, &b);
     if (st) return st;
-    std::vector<TuneChoice> cands;
-    if (b->state_fp32)
-        cands = {{1, 1}, {1, 2}, {1, 4}, {1, 8}, {2, 2}, {2, 4}, {4, 2}, {4, 4}};
-    else
-        cands = {{1, 1, 0}, {2, 1, 0}, {4, 1, 0}, {2, 1, 1}, {4, 1, 1}};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -1395,31 +1422,59 @@ int ljsde_autotune(const ljsde_job *jobs, int n_jobs, void *stream) {
     // batch's choice, also when the tuning fails part-way)
     (void)hipStreamSynchronize((hipStream_t)stream);
     drop_graph(*b);
-    for (const TuneChoice &c : cands) {
+    auto time_one = [&](const TuneChoice &c) -> int {
         int grid = 0;
-        st = grid_for(*b, c, &grid);
-        if (st) break;
+        int st2 = grid_for(*b, c, &grid);
+        if (st2) return st2;
         if (!b->state_fp32) {
-            st = build_groups(*b, c.waves_per_block);
-            if (st) break;
+            st2 = build_groups(*b, c.waves_per_block);
+            if (st2) return st2;
         }
-        st = launch_batch_eager(*b, c, grid, stream);  // warm-up
-        if (st) break;
+        st2 = launch_batch_eager(*b, c, grid, stream);  // warm-up
+        if (st2) return st2;
         float total = 0;
         const int reps = 3;
         (void)hipEventRecord(e0, (hipStream_t)stream);
-        for (int r = 0; r < reps && !st; ++r) st = launch_batch_eager(*b, c, grid, stream);
+        for (int r = 0; r < reps && !st2; ++r) st2 = launch_batch_eager(*b, c, grid, stream);
         (void)hipEventRecord(e1, (hipStream_t)stream);
-        if (st) break;
-        hipError_t e = hipEventSynchronize(e1);
-        if (e != hipSuccess) {
-            st = fail(LJSDE_EHIP, "autotune: %s", hipGetErrorString(e));
-            break;
-        }
+        if (st2) return st2;
+        const hipError_t e = hipEventSynchronize(e1);
+        if (e != hipSuccess) return fail(LJSDE_EHIP, "autotune: %s", hipGetErrorString(e));
         (void)hipEventElapsedTime(&total, e0, e1);
         if (total / reps < best_ms) {
             best_ms = total / reps;
             best = c;
+        }
+        return LJSDE_OK;
+    };
+    if (b->state_fp32) {
+        for (const TuneChoice &c : std::vector<TuneChoice>{
+                 {1, 1}, {1, 2}, {1, 4}, {1, 8}, {2, 2}, {2, 4}, {4, 2}, {4, 4}})
+            if ((st = time_one(c))) break;
+    } else {
+        // stage 1: windows per workgroup and resident workgroups per CU;
+        // stage 2: groups per claim; stage 3: the LDS layout of the per-lane
+        // tables and the DFT tile shape (W = 32 without split-BF16 only)
+        for (const TuneChoice &c : std::vector<TuneChoice>{{1, 1, 0}, {2, 1, 0}, {4, 1, 0}, {2, 1, 1}, {4, 1, 1}})
+            if ((st = time_one(c))) break;
+        if (!st) {
+            const TuneChoice base = best;
+            for (int chunk : {2, 4}) {
+                TuneChoice c = base;
+                c.chunk = chunk;
+                if ((st = time_one(c))) break;
+            }
+        }
+        if (!st && b->ws == 16 && !b->params.dft_bf16) {
+            const TuneChoice base = best;
+            TuneChoice c = base;
+            c.qreg = 1;
+            st = time_one(c);
+            if (!st) {
+                c = base;
+                c.vdft = 1;
+                st = time_one(c);
+            }
         }
     }
     (void)hipEventDestroy(e0);

@@ -85,9 +85,16 @@ int launch_mixed_window(const KParams &p, const KJob &job, int ws, void *stream)
 // Group ranges of the persistent FP32 launch: one per XCD of an MI355X.
 // range_begin holds XCD_RANGES + 1 offsets into the group list.
 constexpr int XCD_RANGES = COUNTERS;
+// Launch variant of the persistent FP32 kernel (the autotuner's knobs).
+struct MixedVariant {
+    int nw = 4;         // windows (wavefronts) per workgroup: 1, 2 or 4
+    int chunk = 1;      // groups taken per claim
+    bool qreg = false;  // per-lane q/D and twiddles in registers instead of LDS
+    bool vdft = false;  // window DFT as VALU passes instead of FP64 MFMA
+};
 int launch_mixed_persistent(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, const int *range_begin,
-                            unsigned int *counters, int ws, int nw, int grid, void *stream);
-int mixed_blocks_per_cu(int ws, int nw, int *blocks);
+                            unsigned int *counters, int ws, const MixedVariant &v, int grid, void *stream);
+int mixed_blocks_per_cu(int ws, const MixedVariant &v, int *blocks);
 // Dense form (ljsde_dense.hip): bytes of the dense C of n classes, its build
 // from the class tables, and the one-wavefront-per-window FP64 launch.
 size_t dense_c_bytes(int ws, int n_classes);
@@ -134,7 +141,7 @@ int noalloc_scratch(int dev, unsigned char **ptr);
 // the array; then one fill kernel writes the job, the ranges and zeroed
 // counters, and the persistent kernel runs on them. Returns a hipError_t value.
 int launch_mixed_noalloc(const KParams &p, const KJob &job, const WinGroup *host_groups, int ngroups,
-                         const int *ranges, bool upload, int ws, int nw, int grid, unsigned char *scr,
-                         void *stream);
+                         const int *ranges, bool upload, int ws, const MixedVariant &v, int grid,
+                         unsigned char *scr, void *stream);
 
 }  // namespace ljsde

@@ -48,7 +48,13 @@ struct MixedLds {
     static constexpr size_t bytes(int nw) { return shared_bytes + nw * wave_bytes; }
 };
 
-template <int WS, bool BF16, int SHAPE>
+// Launch-variant knobs of the FP32 kernels (picked by the autotuner):
+//  QREG  the per-lane q/D and projection twiddles of the window's class are
+//        loaded from LDS into registers once per window (more VGPRs, fewer
+//        LDS reads) instead of being re-read from LDS every iteration;
+//  VDFT  the window DFT runs as VALU row and column passes in FP64 instead
+//        of FP64 MFMA products (the same sums in another order).
+template <int WS, bool BF16, int SHAPE, bool QREG = false, bool VDFT = false>
 __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJob &j, int bi, int bj,
                                                      long long win_local, char *wlds, const char *glds) {
     using LL = MixedLds<WS>;
@@ -106,7 +112,7 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
 
     // ---- FP64 orientation-masked DFT of the window --------------------------
     C2<double> P[QPL][4];
-    if constexpr (WS == 16) {
+    if constexpr (WS == 16 && !VDFT) {
         double Pre[4][4], Pim[4][4];
         if constexpr (BF16) dft16_splitbf16<double>(X, Cd, dft, (float *)stage, Pre, Pim);
         else dft16_mfma<double>(X, Cd, dft, Pre, Pim);
@@ -159,6 +165,14 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
     double outacc = 0.0;
     double E = e0;
     int nu_done = 0;
+    float4 q4r[QREG ? QPL : 1], t4r[QREG ? QPL : 1];
+    if constexpr (QREG) {
+#pragma unroll
+        for (int t = 0; t < QPL; ++t) {
+            q4r[t] = *(const float4 *)(qdl + (t * 64 + lane) * 4);
+            t4r[t] = *(const float4 *)(twl + (t * 64 + lane) * 4);
+        }
+    }
 
 #pragma unroll 1
     for (int nu = 0; nu < p.iters; ++nu) {
@@ -167,14 +181,24 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         unsigned kb = 0u, ks = 0u;
         // per-lane q/D and twiddles of a position are read one position
         // ahead, so their LDS latency overlaps the previous position's work
-        float4 q4n = *(const float4 *)(qdl + lane * 4);
-        float4 t4n = *(const float4 *)(twl + lane * 4);
+        float4 q4n, t4n;
+        if constexpr (!QREG) {
+            q4n = *(const float4 *)(qdl + lane * 4);
+            t4n = *(const float4 *)(twl + lane * 4);
+        }
 #pragma unroll
         for (int t = 0; t < QPL; ++t) {
-            const float4 q4 = q4n, t4 = t4n;
-            if (t + 1 < QPL) {
-                q4n = *(const float4 *)(qdl + ((t + 1) * 64 + lane) * 4);
-                t4n = *(const float4 *)(twl + ((t + 1) * 64 + lane) * 4);
+            float4 q4, t4;
+            if constexpr (QREG) {
+                q4 = q4r[t];
+                t4 = t4r[t];
+            } else {
+                q4 = q4n;
+                t4 = t4n;
+                if (t + 1 < QPL) {
+                    q4n = *(const float4 *)(qdl + ((t + 1) * 64 + lane) * 4);
+                    t4n = *(const float4 *)(twl + ((t + 1) * 64 + lane) * 4);
+                }
             }
             C2<float> Pf[4], R[4];
 #pragma unroll
@@ -384,32 +408,41 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void mi
 // group list is ordered by spatial tile and cut into XCD_RANGES contiguous
 // ranges with one counter each; a workgroup drains the range of its own XCD
 // (workgroups are dealt to the XCDs round-robin) and then the others, so the
-// measurements and output lines of a tile stay in one XCD's L2. Every group
-// index is claimed exactly once whatever the actual placement.
-template <int WS, int NW, bool BF16, int SHAPE>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void mixed_persistent_kernel(KParams p, const KJob *__restrict__ jobs,
-                                                                   const WinGroup *__restrict__ groups,
-                                                                   const int *__restrict__ range_begin,
-                                                                   unsigned int *counters) {
+// measurements and output lines of a tile stay in one XCD's L2. A claim takes
+// `chunk` consecutive groups of a range (runs of one class inside a tile), and
+// the class tables are staged into LDS only when the class changes. Every
+// group index is claimed exactly once whatever the actual placement.
+template <int WS, int NW, bool BF16, int SHAPE, bool QREG, bool VDFT>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(QREG ? 2 : 3))) void mixed_persistent_kernel(
+    KParams p, const KJob *__restrict__ jobs, const WinGroup *__restrict__ groups, const int *__restrict__ range_begin,
+    unsigned int *counters, int chunk) {
     extern __shared__ __align__(16) char lds[];
     using L = MixedLds<WS>;
     int *slot = (int *)(lds + L::offSlot);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     char *wl = lds + L::shared_bytes + (size_t)wave * L::wave_bytes;
     const int home = (int)(blockIdx.x % XCD_RANGES);
-    int tried = 0;  // ranges found exhausted (thread 0 only)
+    int tried = 0;             // ranges found exhausted (thread 0 only)
+    int next = 0, left = 0;    // the current claim (thread 0 only)
+    int staged_job = -1, staged_cls = -1;
     bool first = true;
     for (;;) {
         if (threadIdx.x == 0) {
             int g = -1;
-            while (tried < XCD_RANGES) {
+            while (left == 0 && tried < XCD_RANGES) {
                 const int r = (home + tried) % XCD_RANGES;
-                const int k = (int)atomicAdd(counters + r, 1u);
-                if (k < range_begin[r + 1] - range_begin[r]) {
-                    g = range_begin[r] + k;
-                    break;
+                const int n = range_begin[r + 1] - range_begin[r];
+                const int k = (int)atomicAdd(counters + r, (unsigned)chunk);
+                if (k < n) {
+                    next = range_begin[r] + k;
+                    left = min(chunk, n - k);
+                } else {
+                    ++tried;
                 }
-                ++tried;
+            }
+            if (left > 0) {
+                g = next++;
+                --left;
             }
             *slot = g;
         }
@@ -421,13 +454,17 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
         const int gjob = groups[gi].job, gcount = groups[gi].count;
         const KJob J = jobs[gjob];
         const int w0 = groups[gi].win[0];
-        const int cls = J.rowcls[w0 / J.nbj] * J.ncolk + J.colcls[w0 % J.nbj];
-        stage_tables<WS>(p, J, cls, lds, first);
-        first = false;
+        const int cls = __builtin_amdgcn_readfirstlane(J.rowcls[w0 / J.nbj] * J.ncolk + J.colcls[w0 % J.nbj]);
+        if (gjob != staged_job || cls != staged_cls) {
+            stage_tables<WS>(p, J, cls, lds, first);
+            first = false;
+            staged_job = gjob;
+            staged_cls = cls;
+        }
         __syncthreads();
         if (wave < gcount) {
             const int lw = __builtin_amdgcn_readfirstlane(groups[gi].win[wave]);
-            process_window_mixed<WS, BF16, SHAPE>(p, J, lw / J.nbj, lw % J.nbj, lw, wl, lds);
+            process_window_mixed<WS, BF16, SHAPE, QREG, VDFT>(p, J, lw / J.nbj, lw % J.nbj, lw, wl, lds);
         }
         __syncthreads();
     }
@@ -457,46 +494,81 @@ int launch_mixed_window(const KParams &p, const KJob &job, int ws, void *stream)
                                     : launch_mw<SHAPE_THREE_QUARTER>(p, job, ws, stream);
 }
 
-template <int WS, int NW, bool BF16, int SHAPE>
+template <int WS, int NW, bool BF16, int SHAPE, bool QREG, bool VDFT>
 static int launch_mp(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, const int *range_begin,
-                     unsigned int *counters, int grid, void *stream) {
+                     unsigned int *counters, int chunk, int grid, void *stream) {
     const size_t lds = MixedLds<WS>::bytes(NW);
-    mixed_persistent_kernel<WS, NW, BF16, SHAPE><<<dim3(grid), dim3(64 * NW), lds, (hipStream_t)stream>>>(
-        p, d_jobs, d_groups, range_begin, counters);
+    mixed_persistent_kernel<WS, NW, BF16, SHAPE, QREG, VDFT><<<dim3(grid), dim3(64 * NW), lds, (hipStream_t)stream>>>(
+        p, d_jobs, d_groups, range_begin, counters, chunk);
     return (int)hipGetLastError();
 }
 
-template <int WS, bool BF16, int SHAPE>
+template <int WS, bool BF16, int SHAPE, bool QREG, bool VDFT>
 static int launch_mp_nw(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, const int *range_begin,
-                        unsigned int *counters, int nw, int grid, void *stream) {
-    if (nw == 1) return launch_mp<WS, 1, BF16, SHAPE>(p, d_jobs, d_groups, range_begin, counters, grid, stream);
-    if (nw == 2) return launch_mp<WS, 2, BF16, SHAPE>(p, d_jobs, d_groups, range_begin, counters, grid, stream);
-    return launch_mp<WS, 4, BF16, SHAPE>(p, d_jobs, d_groups, range_begin, counters, grid, stream);
+                        unsigned int *counters, const MixedVariant &v, int grid, void *stream) {
+    if (v.nw == 1)
+        return launch_mp<WS, 1, BF16, SHAPE, QREG, VDFT>(p, d_jobs, d_groups, range_begin, counters, v.chunk, grid,
+                                                         stream);
+    if (v.nw == 2)
+        return launch_mp<WS, 2, BF16, SHAPE, QREG, VDFT>(p, d_jobs, d_groups, range_begin, counters, v.chunk, grid,
+                                                         stream);
+    return launch_mp<WS, 4, BF16, SHAPE, QREG, VDFT>(p, d_jobs, d_groups, range_begin, counters, v.chunk, grid,
+                                                     stream);
+}
+
+// The knobs exist for W = 32 without the split-BF16 DFT; other plans run the
+// default variant.
+template <int SHAPE>
+static int launch_mp_knobs(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, const int *range_begin,
+                           unsigned int *counters, const MixedVariant &v, int grid, void *stream) {
+    if (v.qreg && v.vdft)
+        return launch_mp_nw<16, false, SHAPE, true, true>(p, d_jobs, d_groups, range_begin, counters, v, grid, stream);
+    if (v.qreg)
+        return launch_mp_nw<16, false, SHAPE, true, false>(p, d_jobs, d_groups, range_begin, counters, v, grid, stream);
+    if (v.vdft)
+        return launch_mp_nw<16, false, SHAPE, false, true>(p, d_jobs, d_groups, range_begin, counters, v, grid, stream);
+    return launch_mp_nw<16, false, SHAPE, false, false>(p, d_jobs, d_groups, range_begin, counters, v, grid, stream);
 }
 
 int launch_mixed_persistent(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, const int *range_begin,
-                            unsigned int *counters, int ws, int nw, int grid, void *stream) {
+                            unsigned int *counters, int ws, const MixedVariant &v, int grid, void *stream) {
     constexpr int TQ = SHAPE_THREE_QUARTER, QS = SHAPE_QUARTER;
-    if (p.shape == QS)
-        return ws == 16 ? launch_mp_nw<16, false, QS>(p, d_jobs, d_groups, range_begin, counters, nw, grid, stream)
-                        : launch_mp_nw<8, false, QS>(p, d_jobs, d_groups, range_begin, counters, nw, grid, stream);
+    if (v.nw != 1 && v.nw != 2 && v.nw != 4) return (int)hipErrorInvalidValue;
+    if (v.chunk < 1) return (int)hipErrorInvalidValue;
     if (ws == 16 && p.dft_bf16)
-        return launch_mp_nw<16, true, TQ>(p, d_jobs, d_groups, range_begin, counters, nw, grid, stream);
-    if (ws == 16) return launch_mp_nw<16, false, TQ>(p, d_jobs, d_groups, range_begin, counters, nw, grid, stream);
-    return launch_mp_nw<8, false, TQ>(p, d_jobs, d_groups, range_begin, counters, nw, grid, stream);
+        return launch_mp_nw<16, true, TQ, false, false>(p, d_jobs, d_groups, range_begin, counters, v, grid, stream);
+    if (ws == 16)
+        return p.shape == QS ? launch_mp_knobs<QS>(p, d_jobs, d_groups, range_begin, counters, v, grid, stream)
+                             : launch_mp_knobs<TQ>(p, d_jobs, d_groups, range_begin, counters, v, grid, stream);
+    return p.shape == QS ? launch_mp_nw<8, false, QS, false, false>(p, d_jobs, d_groups, range_begin, counters, v,
+                                                                     grid, stream)
+                         : launch_mp_nw<8, false, TQ, false, false>(p, d_jobs, d_groups, range_begin, counters, v,
+                                                                     grid, stream);
 }
 
-template <int WS, int NW>
+template <int WS, int NW, bool QREG, bool VDFT>
 static int occ_mp(int *blocks) {
     return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        blocks, mixed_persistent_kernel<WS, NW, false, SHAPE_THREE_QUARTER>, 64 * NW, MixedLds<WS>::bytes(NW));
+        blocks, mixed_persistent_kernel<WS, NW, false, SHAPE_THREE_QUARTER, QREG, VDFT>, 64 * NW,
+        MixedLds<WS>::bytes(NW));
+}
+
+template <bool QREG, bool VDFT>
+static int occ_knobs(int ws, int nw, int *blocks) {
+    if (ws == 16)
+        return nw == 1 ? occ_mp<16, 1, QREG, VDFT>(blocks) : nw == 2 ? occ_mp<16, 2, QREG, VDFT>(blocks)
+                                                                     : occ_mp<16, 4, QREG, VDFT>(blocks);
+    return nw == 1 ? occ_mp<8, 1, false, false>(blocks) : nw == 2 ? occ_mp<8, 2, false, false>(blocks)
+                                                                  : occ_mp<8, 4, false, false>(blocks);
 }
 
 // Occupancy of the three-quarter instantiation (the quarter-sampling one uses
 // no more registers or LDS).
-int mixed_blocks_per_cu(int ws, int nw, int *blocks) {
-    if (ws == 16) return nw == 1 ? occ_mp<16, 1>(blocks) : nw == 2 ? occ_mp<16, 2>(blocks) : occ_mp<16, 4>(blocks);
-    return nw == 1 ? occ_mp<8, 1>(blocks) : nw == 2 ? occ_mp<8, 2>(blocks) : occ_mp<8, 4>(blocks);
+int mixed_blocks_per_cu(int ws, const MixedVariant &v, int *blocks) {
+    if (v.qreg && v.vdft) return occ_knobs<true, true>(ws, v.nw, blocks);
+    if (v.qreg) return occ_knobs<true, false>(ws, v.nw, blocks);
+    if (v.vdft) return occ_knobs<false, true>(ws, v.nw, blocks);
+    return occ_knobs<false, false>(ws, v.nw, blocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -541,8 +613,8 @@ int noalloc_scratch(int dev, unsigned char **ptr) {
 }
 
 int launch_mixed_noalloc(const KParams &p, const KJob &job, const WinGroup *host_groups, int ngroups,
-                         const int *ranges, bool upload, int ws, int nw, int grid, unsigned char *scr,
-                         void *stream) {
+                         const int *ranges, bool upload, int ws, const MixedVariant &v, int grid,
+                         unsigned char *scr, void *stream) {
     if (ngroups < 0 || ngroups > NOALLOC_MAX_GROUPS) return (int)hipErrorInvalidValue;
     if (upload && ngroups > 0) {
         const hipError_t e = hipMemcpyAsync(scr + NOALLOC_OFF_GROUPS, host_groups, sizeof(WinGroup) * ngroups,
@@ -556,7 +628,7 @@ int launch_mixed_noalloc(const KParams &p, const KJob &job, const WinGroup *host
     if (e != hipSuccess) return (int)e;
     return launch_mixed_persistent(p, (const KJob *)(scr + NOALLOC_OFF_JOB),
                                    (const WinGroup *)(scr + NOALLOC_OFF_GROUPS),
-                                   (const int *)(scr + NOALLOC_OFF_RANGES), (unsigned int *)scr, ws, nw, grid,
+                                   (const int *)(scr + NOALLOC_OFF_RANGES), (unsigned int *)scr, ws, v, grid,
                                    stream);
 }
 

@@ -298,13 +298,54 @@ def test_autotune_keeps_results_and_writes_its_cache(L, tmp_path, monkeypatch):
         o.zero_()
     L.reconstruct_batch(items)
     torch.cuda.synchronize()
-    for b, (_, _, o) in zip(before, items):
-        assert torch.equal(b, o)
     import json
     tuned = json.loads(cache.read_text())
     assert len(tuned) >= 1
     for v in tuned.values():
-        assert len(v) == 3 and v[0] in (1, 2, 4) and v[2] in (0, 1)
+        # windows per workgroup, groups per claim, fewer workgroups per CU,
+        # q/D and twiddles in registers, VALU window DFT
+        assert len(v) == 5 and v[0] in (1, 2, 4) and v[1] in (1, 2, 4) and v[2] in (0, 1)
+        assert v[3] in (0, 1) and v[4] in (0, 1)
+    vdft = any(v[4] for v in tuned.values())
+    for b, (_, _, o) in zip(before, items):
+        # the VALU DFT sums in another order (FP64): equal up to rounding
+        assert torch.equal(b, o) if not vdft else float(torch.max(torch.abs(b - o))) <= 1e-3
+    for _, pid, _ in items:
+        L.release(pid)
+
+
+@pytest.mark.parametrize("variant", ["1,1,0,0,0", "2,2,0,0,0", "4,4,1,0,0", "4,1,0,1,0", "2,4,0,1,0",
+                                     "4,1,0,0,1", "1,2,1,1,1"])
+def test_every_launch_variant_gives_the_same_images(L, monkeypatch, variant):
+    """The autotuner's knobs (windows per workgroup, groups per claim,
+    resident workgroups per CU, q/D and twiddles in registers or LDS, window
+    DFT on FP64 MFMA or as VALU passes), forced one at a time: the batched
+    images equal the diagnostic single-image calls bitwise, and within FP64
+    rounding of the DFT's summation order for the VALU DFT."""
+    monkeypatch.setenv("LJSDE_VARIANT", variant)
+    vdft = variant.endswith(",1")
+    items, singles = [], []
+    for k, (r, cc, per) in enumerate([(96, 80, 2), (64, 120, 4), (72, 72, 8), (40, 48, 4)]):
+        case = make_case(r, cc, per, seed=90 + k)
+        pid = L.plan(case["tile"], iters=30, input_f64=True)
+        y = _dev(case["y"], np.float64)
+        items.append((y, pid, torch.full((r, cc), float("nan"), dtype=torch.float32, device="cuda:0")))
+        singles.append(L.reconstruct_diag(y, pid)[0].clone())
+    print(f"launch variant {variant}", flush=True)
+    for rep in range(2):
+        L.reconstruct_batch(items)
+        torch.cuda.synchronize()
+        for (_, _, o), s in zip(items, singles):
+            if vdft:
+                assert float(torch.max(torch.abs(o - s))) <= 1e-3
+            else:
+                assert torch.equal(o, s), rep
+    # the allocation-free call takes the forced variant too
+    y, pid, o = items[0]
+    out = torch.full_like(o, float("nan"))
+    L.reconstruct_noalloc(y, pid, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, o)
     for _, pid, _ in items:
         L.release(pid)
 
