@@ -57,7 +57,7 @@ enum {
     LJSDE_DFT_SPLITBF16 = 4,  /* FP32 plans, W = 32: window DFT on MFMA with 3-term split-BF16
                                  products and FP32 accumulation instead of FP64 MFMA (relative
                                  error ~2^-16 in the initial state; selections can then
-                                 diverge from FP64 at near ties) */
+                                 diverge from FP64 at near ties). With LJSDE_STATE_FP32 also */
     LJSDE_Q_ONES = 8,         /* frequency weight q = 1 (test mode) */
     LJSDE_STATE_FP32 = 16,    /* FP32 plans: keep the loop state and its updates in FP32 too
                                  (no FP64 re-decision); greedy selections can then diverge

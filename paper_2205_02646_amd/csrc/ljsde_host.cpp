@@ -1049,8 +1049,8 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, i
         return fail(LJSDE_EINVAL, "LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32 do not apply to the dense form");
     if (!(window == 32 || window == 16))
         return fail(LJSDE_EUNSUPPORTED, "no kernel for window %d (have 16, 32)", window);
-    if ((flags & LJSDE_DFT_SPLITBF16) && ((flags & LJSDE_STATE_FP32) || window != 32))
-        return fail(LJSDE_EUNSUPPORTED, "LJSDE_DFT_SPLITBF16 needs window 32 and the FP64 loop state");
+    if ((flags & LJSDE_DFT_SPLITBF16) && window != 32)
+        return fail(LJSDE_EUNSUPPORTED, "LJSDE_DFT_SPLITBF16 needs window 32");
     if (!(block == 4 || block == 8))
         return fail(LJSDE_EUNSUPPORTED, "no kernel for block %d (have 4, 8)", block);
     if (iters > 32767) return fail(LJSDE_EUNSUPPORTED, "iters %d above 32767", iters);

@@ -62,7 +62,14 @@ __device__ __forceinline__ double window_prologue(const KParams &p, const KJob &
     // ---- orientation-masked weighted DFT -----------------------------------
     if constexpr (WS == 16) {
         double Pre[4][4], Pim[4][4];
-        dft16_mfma<T, WEIGHTED>(ldsX, ldsC, p.c.dft, Pre, Pim, Aw);
+        if constexpr (sizeof(T) == 4 && !WEIGHTED) {
+            // FP32-state plans may take the split-BF16 MFMA products (FP32
+            // accumulation); ldsS (8 KiB here) is free until the spectra are staged
+            if (p.dft_bf16) dft16_splitbf16<T>(ldsX, ldsC, p.c.dft, (float *)ldsS, Pre, Pim);
+            else dft16_mfma<T, WEIGHTED>(ldsX, ldsC, p.c.dft, Pre, Pim, Aw);
+        } else {
+            dft16_mfma<T, WEIGHTED>(ldsX, ldsC, p.c.dft, Pre, Pim, Aw);
+        }
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll

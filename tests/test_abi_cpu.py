@@ -53,7 +53,6 @@ TILE = random_pattern(4, 4, seed=0)
     (dict(window=32, block=12), ljsde.EUNSUPPORTED),
     (dict(fp64=True, splitbf16=True), ljsde.EINVAL),
     (dict(fp64=True, state_fp32=True), ljsde.EINVAL),
-    (dict(splitbf16=True, state_fp32=True), ljsde.EUNSUPPORTED),
     (dict(splitbf16=True, window=16), ljsde.EUNSUPPORTED),
     (dict(dense_c=True, splitbf16=True), ljsde.EINVAL),   # options of the factorised FP32 kernel
     (dict(dense_c=True, state_fp32=True), ljsde.EINVAL),
@@ -215,6 +214,15 @@ def test_shape_flags_are_kept_and_default_to_three_quarter():
     assert (ljsde.plan_info(p2)["flags"] >> 8) & 15 == 0xE
     for p in (p0, p1, p2):
         ljsde.release(p)
+
+
+def test_full_reduced_precision_recipe_is_a_valid_plan():
+    """LJSDE_STATE_FP32 with LJSDE_DFT_SPLITBF16 (W = 32): FP32 state, updates
+    and projections with the split-BF16 window DFT."""
+    pid = ljsde.plan(TILE, iters=5, state_fp32=True, splitbf16=True)
+    f = ljsde.plan_info(pid)["flags"]
+    assert f & ljsde.STATE_FP32 and f & ljsde.DFT_SPLITBF16
+    ljsde.release(pid)
 
 
 def test_float64_input_flag_is_accepted_and_kept():
