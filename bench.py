@@ -20,8 +20,10 @@ under quarter sampling: one transparent quadrant per pixel), dense512 (the
 weights512 (a 512x512 frame under a recurrent 4x4 general layout of per-pixel
 quadrant weights, dense form, FP64), ljsde64 (a 64x64 frame with a
 non-recurrent pattern, plain L-JSDE in FP64: the paper's baseline method) and
-ljsde256 (a 256x256 frame with a recurrent 4x4-sensor pattern, plain L-JSDE),
-each timed beside the recurrent FP64 and FP32 batched paths on the same input.
+ljsde256 / ljsde512 (256x256 / 512x512 frames with a recurrent 4x4-sensor
+pattern) and ljsde1200 (the paper's 1200x1200 shape with its 32-pixel period,
+the comparison of its Table II), plain L-JSDE, each timed beside the recurrent
+FP64 and FP32 batched paths on the same input.
 
 Prints one JSON line.
 """
@@ -85,6 +87,10 @@ WORKLOADS.update({
                          "plain L-JSDE FP64"),
     "ljsde256": dict(kind="frame", rows=256, cols=256, period=4, iters=100, noise=0.0, path="plain_l",
                      desc="256x256 frame, recurrent 4x4-sensor pattern, plain L-JSDE FP64"),
+    "ljsde512": dict(kind="frame", rows=512, cols=512, period=4, iters=100, noise=0.0, path="plain_l",
+                     desc="512x512 frame, recurrent 4x4-sensor pattern, plain L-JSDE FP64"),
+    "ljsde1200": dict(kind="frame", rows=1200, cols=1200, period=16, iters=100, noise=0.0, path="plain_l",
+                      desc="1200x1200 frame, recurrent 16x16-sensor pattern (period 32 px), plain L-JSDE FP64"),
 })
 PEAK_FP64_MFMA = 78.6e12          # MI355X FP64 matrix peak, FLOP/s
 HBM_PEAK_GBPS = 8000.0            # MI355X HBM3E
@@ -667,7 +673,12 @@ def main():
     flops = nwin * iters * W * W * FLOPS_PER_FREQ_ITER
     achieved = flops / (ms32 * 1e-3)
     ybytes = 4 if y32_input else 8
-    hbm_bytes = ybytes * sum(y.size for y in ys) + 4 * px      # measurements in, float32 image out
+    # measurements in, float32 image out, and the class tables the kernel reads
+    # once per launch: the weighted-mask spectra (FP64), q/D (FP32) and codes
+    n_classes = sum(ljsde.class_map(j[1], j[0].shape[0], j[0].shape[1])[0] for j in jobs)
+    ws_ = W // 2
+    table_bytes = n_classes * (ws_ * ws_ * 4 * 16 + W * W * 4 + ws_ * ws_)
+    hbm_bytes = ybytes * sum(y.size for y in ys) + 4 * px + table_bytes
     rec = {
         "metric": METRIC,
         "value": mp / (ms32 * 1e-3),
@@ -703,6 +714,7 @@ def main():
                      "traffic": None if args.recipe else load_traffic(args.workload), "kernel_hash": kernel_hash(),
                      "algorithmic_flops_per_launch": flops,
                      "algorithmic_hbm_bytes_per_launch": hbm_bytes,
+                     "class_tables": {"classes": n_classes, "bytes": table_bytes},
                      "peak_unpacked": PEAK_FP32_VALU / 2e12,
                      "frac_of_peak_unpacked": 2 * achieved / PEAK_FP32_VALU,
                      "lds": {"bytes_per_window_iteration": LDS_BYTES_PER_WIN_ITER,

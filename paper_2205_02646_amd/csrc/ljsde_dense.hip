@@ -141,8 +141,11 @@ struct DenseLds {
 // (per-pixel quadrant weights: P_q of every quadrant, R = sum_q conj(e_q) P_q).
 // IO is the element type of the output (FP32 plans: float; the arithmetic is
 // FP64 either way); the measurements are double or float by the job's flag.
-template <int WS, int SHAPE, typename IO>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void dense_kernel(
+// HALVES = 2 reads the column of eq. (17) in two halves through the same
+// registers (the second after the first half's update): 4 wavefronts per
+// SIMD instead of 3, at the price of a second exposed load latency.
+template <int WS, int SHAPE, typename IO, int HALVES>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HALVES == 2 ? 4 : 3))) void dense_kernel(
     KParams p, KJob j, const double2 *__restrict__ Cd, const int *__restrict__ order) {
     extern __shared__ __align__(16) char lds[];
     constexpr int W = 2 * WS, NF = W * W, NPOS = WS * WS, QPL = NPOS / 64, KSTEP = 64 / WS;
@@ -210,9 +213,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void de
 
         // eq. (17) needs column (u, v) of C: start its loads now
         const double2 *col = Cc + (size_t)idx * NF + lane;
-        double2 cv[QPL][4];
+        constexpr int TH = QPL / HALVES > 0 ? QPL / HALVES : 1;  // positions per half
+        double2 cv[TH][4];
 #pragma unroll
-        for (int t = 0; t < QPL; ++t)
+        for (int t = 0; t < TH; ++t)
 #pragma unroll
             for (int c = 0; c < 4; ++c) cv[t][c] = col[(4 * t + c) * 64];
         const double id = invD[idx];
@@ -245,12 +249,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void de
 
         // eq. (17): R -= gamma delta C(:, (u, v))
 #pragma unroll
-        for (int t = 0; t < QPL; ++t)
+        for (int h = 0; h * TH < QPL; ++h) {
+            if (h > 0) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {  // two fused multiply-adds per component
-                R[t][c].re = fma(-gr, cv[t][c].x, fma(gi, cv[t][c].y, R[t][c].re));
-                R[t][c].im = fma(-gr, cv[t][c].y, fma(-gi, cv[t][c].x, R[t][c].im));
+                for (int t = 0; t < TH; ++t)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) cv[t][c] = col[(4 * (h * TH + t) + c) * 64];
             }
+#pragma unroll
+            for (int t = 0; t < TH; ++t)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {  // two fused multiply-adds per component
+                    C2<double> &r = R[h * TH + t][c];
+                    r.re = fma(-gr, cv[t][c].x, fma(gi, cv[t][c].y, r.re));
+                    r.im = fma(-gr, cv[t][c].y, fma(-gi, cv[t][c].x, r.im));
+                }
+        }
     }
     if (j.sel != nullptr)
         for (int nu = nu_done + lane; nu < p.iters; nu += 64) j.sel[w * p.iters + nu] = -1;
@@ -286,7 +300,11 @@ template <int WS, int SHAPE, typename IO>
 static int launch_dense_t(const KParams &p, const KJob &job, const void *C, const int *order, int n,
                           void *stream) {
     if (n <= 0) return 0;
-    dense_kernel<WS, SHAPE, IO><<<dim3((unsigned)n), dim3(64), DenseLds<WS>::bytes, (hipStream_t)stream>>>(
+    // W = 32: the column in two halves (measured 1.04x over one piece: the
+    // fourth wavefront per SIMD hides more of the pick-dependent load latency
+    // than the second exposed latency costs); W = 16 holds one position per lane
+    constexpr int HALVES = WS == 16 ? 2 : 1;
+    dense_kernel<WS, SHAPE, IO, HALVES><<<dim3((unsigned)n), dim3(64), DenseLds<WS>::bytes, (hipStream_t)stream>>>(
         p, job, (const double2 *)C, order);
     return (int)hipGetLastError();
 }

@@ -704,17 +704,31 @@ int grid_for_shape(int ws, bool state_fp32, const TuneChoice &c, int *grid) {
 int grid_for(const BatchState &b, const TuneChoice &c, int *grid) { return grid_for_shape(b.ws, b.state_fp32, c, grid); }
 
 // Work list of the persistent FP32 launch: groups of up to nw windows of one
-// class (they share the class tables staged in LDS). Windows are grouped
-// inside spatial tiles of the block grid, at least twice the class period on
-// each axis (the number of row / column keys bounds that period), so a group
-// is four nearby windows, and the tiles are listed in row-major order. The
-// list is cut into XCD_RANGES contiguous ranges of equal length.
+// class (they share the class tables staged in LDS). Interior windows (no
+// clip on either axis) are grouped inside spatial tiles of the block grid,
+// at least twice the class period on each axis (the number of row / column
+// keys bounds that period), so a group is four nearby windows, and the tiles
+// are listed in row-major order. Windows clipped by the image border follow,
+// listed class by class: a border class runs along a whole image edge, so
+// inside the tiles its tables would be fetched by every XCD whose range
+// crosses that edge. The list is cut into XCD_RANGES contiguous ranges of
+// equal length.
 void make_group_list(const std::vector<const SizeSet *> &sizes, int nw, std::vector<WinGroup> &groups,
                      int ranges[XCD_RANGES + 1]) {
     groups.clear();
+    auto emit = [&](int job, const std::vector<int> &ws) {
+        for (size_t k = 0; k < ws.size(); k += nw) {
+            WinGroup g{};
+            g.job = job;
+            g.count = (int)std::min<size_t>(nw, ws.size() - k);
+            for (int w = 0; w < 4; ++w) g.win[w] = ws[k + std::min(w, g.count - 1)];
+            groups.push_back(g);
+        }
+    };
     for (size_t ji = 0; ji < sizes.size(); ++ji) {
         const SizeSet &s = *sizes[ji];
         const int nck = (int)s.colkeys.size();
+        auto interior = [&](const AxisKey &k) { return k.lo == 0 && k.hi == 0; };
         const int tr = std::min(s.nbi, std::max(16, 2 * (int)s.rowkeys.size()));
         const int tc = std::min(s.nbj, std::max(16, 2 * (int)s.colkeys.size()));
         std::vector<std::vector<int>> by_class(s.n_classes());
@@ -723,23 +737,26 @@ void make_group_list(const std::vector<const SizeSet *> &sizes, int nw, std::vec
             for (int c0 = 0; c0 < s.nbj; c0 += tc) {
                 for (int bi = r0; bi < std::min(s.nbi, r0 + tr); ++bi)
                     for (int bj = c0; bj < std::min(s.nbj, c0 + tc); ++bj) {
+                        if (!interior(s.rowkeys[s.rowcls[bi]]) || !interior(s.colkeys[s.colcls[bj]])) continue;
                         const int cls = s.rowcls[bi] * nck + s.colcls[bj];
                         if (by_class[cls].empty()) used.push_back(cls);
                         by_class[cls].push_back(bi * s.nbj + bj);
                     }
                 for (int cls : used) {
-                    const std::vector<int> &ws = by_class[cls];
-                    for (size_t k = 0; k < ws.size(); k += nw) {
-                        WinGroup g{};
-                        g.job = (int)ji;
-                        g.count = (int)std::min<size_t>(nw, ws.size() - k);
-                        for (int w = 0; w < 4; ++w) g.win[w] = ws[k + std::min(w, g.count - 1)];
-                        groups.push_back(g);
-                    }
+                    emit((int)ji, by_class[cls]);
                     by_class[cls].clear();
                 }
                 used.clear();
             }
+        // border windows, class by class (row-major inside a class)
+        for (int bi = 0; bi < s.nbi; ++bi)
+            for (int bj = 0; bj < s.nbj; ++bj)
+                if (!interior(s.rowkeys[s.rowcls[bi]]) || !interior(s.colkeys[s.colcls[bj]]))
+                    by_class[s.rowcls[bi] * nck + s.colcls[bj]].push_back(bi * s.nbj + bj);
+        for (int cls = 0; cls < s.n_classes(); ++cls) {
+            if (!by_class[cls].empty()) emit((int)ji, by_class[cls]);
+            by_class[cls].clear();
+        }
     }
     for (int r = 0; r <= XCD_RANGES; ++r) ranges[r] = (int)((long long)groups.size() * r / XCD_RANGES);
 }

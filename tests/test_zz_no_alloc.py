@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import ljsde_oracle as O
-from synth import random_pattern, sense, synthetic_image
+from synth import QUARTER, THREE_QUARTER, random_pattern, sense, synthetic_image
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -26,21 +26,23 @@ def L():
     return ljsde
 
 
-def _image(rows, cols, tile, seed):
+def _image(rows, cols, tile, seed, shape=THREE_QUARTER):
     _, observed = synthetic_image(rows, cols, seed=seed)
-    return sense(observed, tile)
+    return sense(observed, tile, shape)
 
 
-@pytest.mark.parametrize("input_f64", [True, False])
-def test_noalloc_equals_reconstruct_on_consecutive_calls_second_smaller(L, input_f64):
+@pytest.mark.parametrize("input_f64,shape", [(True, THREE_QUARTER), (False, THREE_QUARTER), (True, QUARTER)],
+                         ids=["f64in", "f32in", "quarter_f64in"])
+def test_noalloc_equals_reconstruct_on_consecutive_calls_second_smaller(L, input_f64, shape):
     tile = random_pattern(4, 4, seed=31)
     iters = 40
-    pid = L.plan(tile, window=32, block=4, iters=iters, rho=0.7, gamma=0.5, input_f64=input_f64)
+    pid = L.plan(tile, window=32, block=4, iters=iters, rho=0.7, gamma=0.5, input_f64=input_f64,
+                 shape=0 if shape == THREE_QUARTER else shape)
     dt = torch.float64 if input_f64 else torch.float32
     sizes = [(192, 160), (72, 88)]  # reconstruction rows x cols; the second is smaller
     ys, refs = [], []
     for k, (r, c) in enumerate(sizes):
-        y = _image(r, c, tile, seed=40 + k)
+        y = _image(r, c, tile, seed=40 + k, shape=shape)
         yd = torch.from_numpy(y).to("cuda:0").to(dt).contiguous()
         ys.append((y, yd))
         refs.append(L.reconstruct(yd, pid))  # allocating path: also builds the size's tables
@@ -49,13 +51,13 @@ def test_noalloc_equals_reconstruct_on_consecutive_calls_second_smaller(L, input
     # two calls in a row, the second with the smaller input, then the first again
     for k in (0, 1, 0):
         outs[k].fill_(float("nan"))
-        print(f"noalloc call: input_f64={input_f64} size={sizes[k]}", flush=True)
+        print(f"noalloc call: input_f64={input_f64} shape={shape:#x} size={sizes[k]}", flush=True)
         L.reconstruct_noalloc(ys[k][1], pid, outs[k])
         torch.cuda.synchronize()
         assert torch.equal(outs[k], refs[k]), float(torch.max(torch.abs(outs[k] - refs[k])))
     # the smaller image against the FP64 oracle on the same measurements
     y_small = ys[1][0] if input_f64 else ys[1][0].astype(np.float32).astype(np.float64)
-    ref64 = O.reconstruct(y_small, tile, W=32, B=4, iters=iters, rho=0.7, gamma=0.5, form="RL")
+    ref64 = O.reconstruct(y_small, tile, W=32, B=4, iters=iters, rho=0.7, gamma=0.5, form="RL", shape=shape)
     err = float(np.max(np.abs(outs[1].cpu().numpy().astype(np.float64) - ref64)))
     assert err <= FP32_TOL, err
     L.release(pid)
