@@ -68,7 +68,7 @@ enum {
                                  image size; LJSDE_ENOMEM if it does not fit), each window
                                  keeps R of eq. (12) for all W^2 frequencies and subtracts a
                                  column of C per iteration (eq. (17)). Same results as the
-                                 factorised FP64 path; single-image calls only. With
+                                 factorised FP64 path; single images and batches. With
                                  LJSDE_FP32 the output is float (and the measurements unless
                                  LJSDE_INPUT_F64; the arithmetic stays FP64); not with
                                  LJSDE_DFT_SPLITBF16 or
@@ -79,7 +79,7 @@ enum {
                                  float). The kernels widen every measurement to FP64 on load,
                                  so an FP32 plan then sees exactly the input an FP64 plan sees.
                                  Implied by LJSDE_FP64 */
-    LJSDE_PLAIN_L = 4096      /* FP64 plans: plain L-JSDE (Sec. III; Sec. IV eqs. (4)-(10), (15),
+    LJSDE_PLAIN_L = 4096      /* plain L-JSDE (Sec. III; Sec. IV eqs. (4)-(10), (15),
                                  (16)), the method the recurrent form accelerates. Each window
                                  keeps its residual in the measurement domain and evaluates the
                                  numerator of eq. (10) for every basis function in every
@@ -88,9 +88,11 @@ enum {
                                  responses of every local measurement matrix of an image size are
                                  built in device memory on its first reconstruction (16 B x
                                  (W/2)^2 x W^2 per class: 4 MiB at W = 32; LJSDE_ENOMEM if they
-                                 do not fit). Same results as the recurrent form. Single-image
-                                 calls only; not with LJSDE_DENSE_C. Every pixel shape and
-                                 ljsde_plan_weights layouts */
+                                 do not fit). Same results as the recurrent form. FP64 arithmetic;
+                                 with LJSDE_FP32 the output is float (and the measurements unless
+                                 LJSDE_INPUT_F64). Single-image calls only; not with
+                                 LJSDE_DENSE_C, LJSDE_DFT_SPLITBF16 or LJSDE_STATE_FP32. Every
+                                 pixel shape and ljsde_plan_weights layouts */
 };
 
 /*
@@ -157,7 +159,7 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols,
  *  flags     LJSDE_DENSE_C with LJSDE_FP64 (double measurements and output)
  *            or LJSDE_FP32 (float output, and float measurements unless
  *            LJSDE_INPUT_F64; FP64 arithmetic either way), or LJSDE_PLAIN_L
- *            with LJSDE_FP64; optionally LJSDE_Q_ONES; no pixel shape.
+ *            with either; optionally LJSDE_Q_ONES; no pixel shape.
  *            Without LJSDE_DENSE_C or LJSDE_PLAIN_L -> LJSDE_EUNSUPPORTED.
  * Per class the tables hold the ten spectra S_qq' = DFT(w A_q A_q') (q <= q')
  * and the per-pixel weights; C of eq. (14) is built from them on the device.
@@ -213,20 +215,28 @@ typedef struct {
                                  job's plan: jobs of one batch may differ) */
     int sensor_rows;
     int sensor_cols;
-    int pattern_id;           /* FP32 plans with equal window, block and iters */
+    int pattern_id;           /* see ljsde_reconstruct_batch for the plans one batch may mix */
     void *out;                /* device */
 } ljsde_job;
 
 /*
  * ljsde_reconstruct_batch -- reconstruct many images of uneven size and
- * pattern in one persistent launch, captured once as a HIP graph per batch
- * shape and stream and replayed afterwards (device state per batch shape and
- * stream, kept until a plan of the batch is released; launches on different
- * streams may overlap). All jobs must use FP32 plans of the factorised form
- * with the same window, block and iteration count. `jobs` is host memory,
- * read during the call only; an empty batch is LJSDE_EINVAL, and so is a
- * job whose measurements or out are not device memory (checked whenever a
- * job's buffers change; nothing is launched then).
+ * pattern in one launch (device state per batch shape and stream, kept until
+ * a plan of the batch is released; launches on different streams may
+ * overlap). Two kinds of batch, by the first job's plan:
+ *  - FP32 plans of the factorised form: one persistent launch, captured once
+ *    as a HIP graph per batch shape and stream and replayed afterwards. All
+ *    plans need equal window, block, iterations, rho, gamma, energy floor,
+ *    state precision, DFT mode and pixel shape (LJSDE_EINVAL otherwise).
+ *  - plans of the dense form (LJSDE_DENSE_C, FP64 or FP32): one launch over
+ *    the windows of all images, each image with its own dense C (built on
+ *    the first use of its plan and size). All plans need the dense form and
+ *    equal window, block, iterations, rho, gamma, energy floor, pixel shape
+ *    and precision (LJSDE_EINVAL otherwise).
+ * Other plans (FP64 factorised, LJSDE_PLAIN_L) -> LJSDE_EUNSUPPORTED.
+ * `jobs` is host memory, read during the call only; an empty batch is
+ * LJSDE_EINVAL, and so is a job whose measurements or out are not device
+ * memory (checked whenever a job's buffers change; nothing is launched then).
  */
 int ljsde_reconstruct_batch(const ljsde_job *jobs, int n_jobs, void *stream);
 
@@ -239,8 +249,8 @@ int ljsde_reconstruct_batch(const ljsde_job *jobs, int n_jobs, void *stream);
  * device array of the library, one per GPU, held until the process ends.
  *  measurements, sensor_rows, sensor_cols, pattern_id, out, stream
  *            as for ljsde_reconstruct. FP32 plans of the factorised form
- *            only (LJSDE_FP64, LJSDE_DENSE_C and LJSDE_STATE_FP32 plans ->
- *            LJSDE_EUNSUPPORTED).
+ *            only (LJSDE_FP64, LJSDE_DENSE_C, LJSDE_STATE_FP32 and
+ *            LJSDE_PLAIN_L plans -> LJSDE_EUNSUPPORTED).
  * Precondition: the plan has already reconstructed an image of this sensor
  * size on this device (ljsde_reconstruct, ljsde_reconstruct_batch or
  * ljsde_reconstruct_diag build and upload its class tables); otherwise

@@ -145,12 +145,9 @@ struct DenseLds {
 // registers (the second after the first half's update): 4 wavefronts per
 // SIMD instead of 3, at the price of a second exposed load latency.
 template <int WS, int SHAPE, typename IO, int HALVES>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HALVES == 2 ? 4 : 3))) void dense_kernel(
-    KParams p, KJob j, const double2 *__restrict__ Cd, const int *__restrict__ order) {
-    extern __shared__ __align__(16) char lds[];
+__device__ __forceinline__ void dense_window(const KParams &p, const KJob &j, const double2 *__restrict__ Cd, int wo,
+                                             char *lds) {
     constexpr int W = 2 * WS, NF = W * W, NPOS = WS * WS, QPL = NPOS / 64, KSTEP = 64 / WS;
-    const int wo = order[blockIdx.x];  // workgroup -> window (class-sorted, per-XCD chunks)
-    if (wo < 0) return;
     const long long w = wo;
     const int bi = (int)(w / j.nbj), bj = (int)(w % j.nbj);
     const int lane = threadIdx.x & 63;
@@ -275,6 +272,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HALVES == 2 
     }
 }
 
+// One image: workgroup b runs window order[b] (class-sorted, per-XCD chunks).
+template <int WS, int SHAPE, typename IO, int HALVES>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HALVES == 2 ? 4 : 3))) void dense_kernel(
+    KParams p, KJob j, const double2 *__restrict__ Cd, const int *__restrict__ order) {
+    extern __shared__ __align__(16) char lds[];
+    const int wo = order[blockIdx.x];
+    if (wo < 0) return;
+    dense_window<WS, SHAPE, IO, HALVES>(p, j, Cd, wo, lds);
+}
+
+// Many images in one launch: workgroup b runs window order[b].y of job
+// order[b].x (x < 0: idle), with the job's own dense C.
+template <int WS, int SHAPE, typename IO, int HALVES>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HALVES == 2 ? 4 : 3))) void dense_batch_kernel(
+    KParams p, const KJob *__restrict__ jobs, const int2 *__restrict__ order) {
+    extern __shared__ __align__(16) char lds[];
+    const int2 e = order[blockIdx.x];
+    if (e.x < 0) return;
+    const KJob J = jobs[e.x];
+    dense_window<WS, SHAPE, IO, HALVES>(p, J, (const double2 *)J.dense, e.y, lds);
+}
+
 size_t dense_c_bytes(int ws, int n_classes) {
     const size_t nf = (size_t)(2 * ws) * (2 * ws);
     return (size_t)n_classes * nf * nf * sizeof(double2);
@@ -321,6 +340,35 @@ static int launch_dense_io(const KParams &p, const KJob &job, const void *C, con
                         : launch_dense_t<8, QS, IO>(p, job, C, order, n, stream);
     return ws == 16 ? launch_dense_t<16, TQ, IO>(p, job, C, order, n, stream)
                     : launch_dense_t<8, TQ, IO>(p, job, C, order, n, stream);
+}
+
+template <int WS, int SHAPE, typename IO>
+static int launch_dense_batch_t(const KParams &p, const KJob *jobs, const void *order, int n, void *stream) {
+    if (n <= 0) return 0;
+    constexpr int HALVES = WS == 16 ? 2 : 1;
+    dense_batch_kernel<WS, SHAPE, IO, HALVES>
+        <<<dim3((unsigned)n), dim3(64), DenseLds<WS>::bytes, (hipStream_t)stream>>>(p, jobs, (const int2 *)order);
+    return (int)hipGetLastError();
+}
+
+template <typename IO>
+static int launch_dense_batch_io(const KParams &p, const KJob *jobs, const void *order, int n, int ws,
+                                 void *stream) {
+    constexpr int TQ = SHAPE_THREE_QUARTER, QS = SHAPE_QUARTER, GN = SHAPE_GENERAL;
+    if (p.shape == GN)
+        return ws == 16 ? launch_dense_batch_t<16, GN, IO>(p, jobs, order, n, stream)
+                        : launch_dense_batch_t<8, GN, IO>(p, jobs, order, n, stream);
+    if (p.shape == QS)
+        return ws == 16 ? launch_dense_batch_t<16, QS, IO>(p, jobs, order, n, stream)
+                        : launch_dense_batch_t<8, QS, IO>(p, jobs, order, n, stream);
+    return ws == 16 ? launch_dense_batch_t<16, TQ, IO>(p, jobs, order, n, stream)
+                    : launch_dense_batch_t<8, TQ, IO>(p, jobs, order, n, stream);
+}
+
+int launch_dense_batch(const KParams &p, const KJob *jobs, const void *order, int n, int ws, bool f32io,
+                       void *stream) {
+    return f32io ? launch_dense_batch_io<float>(p, jobs, order, n, ws, stream)
+                 : launch_dense_batch_io<double>(p, jobs, order, n, ws, stream);
 }
 
 int launch_dense(const KParams &p, const KJob &job, const void *C, const int *order, int n, int ws, bool f32io,

@@ -603,6 +603,23 @@ struct BatchState {
 };
 
 std::map<std::string, std::unique_ptr<BatchState>> g_batches;
+
+// Batched dense form: the job table and the launch order, (job, window) per
+// workgroup, kept per batch shape and stream like the FP32 batch states.
+struct DenseBatch {
+    std::vector<KJob> host_jobs;
+    KJob *d_jobs = nullptr;
+    int *d_order = nullptr;  // int2 [n_order]
+    int n_order = 0;
+    KParams params{};
+    int ws = 16;
+    bool f32io = false;
+    ~DenseBatch() {
+        if (d_jobs) (void)hipFree(d_jobs);
+        if (d_order) (void)hipFree(d_order);
+    }
+};
+std::map<std::string, std::unique_ptr<DenseBatch>> g_dense_batches;
 std::map<std::string, TuneChoice> g_tuned;
 hipStream_t g_capture_stream = nullptr;
 
@@ -821,12 +838,14 @@ int prepare_batch(const ljsde_job *jobs, int n, void *stream, BatchState **out) 
         st = get_plan(jobs[i].pattern_id, &p);
         if (st) return st;
         if (p->fp64()) return fail(LJSDE_EUNSUPPORTED, "job %d: batched launches need FP32 plans", i);
-        if (p->flags & LJSDE_DENSE_C)
+        if (p->flags & (LJSDE_DENSE_C | LJSDE_PLAIN_L))
             return fail(LJSDE_EUNSUPPORTED, "job %d: batched launches need FP32 plans of the factorised form", i);
+        // one launch reads the class-independent tables (spatial weights of
+        // eq. (8), pixel responses) of the first plan
         if (p->W != p0->W || p->B != p0->B || p->iters != p0->iters || p->gamma != p0->gamma ||
-            p->tau != p0->tau || ((p->flags & LJSDE_STATE_FP32) != 0) != sf32 || p->shape != p0->shape ||
-            ((p->flags ^ p0->flags) & LJSDE_DFT_SPLITBF16))
-            return fail(LJSDE_EINVAL, "job %d: all plans of a batch need equal window, block, iters, "
+            p->rho != p0->rho || p->tau != p0->tau || ((p->flags & LJSDE_STATE_FP32) != 0) != sf32 ||
+            p->shape != p0->shape || ((p->flags ^ p0->flags) & LJSDE_DFT_SPLITBF16))
+            return fail(LJSDE_EINVAL, "job %d: all plans of a batch need equal window, block, iters, rho, "
                                       "gamma, energy floor, state precision, DFT mode and pixel shape", i);
         if (!jobs[i].measurements || !jobs[i].out)
             return fail(LJSDE_EINVAL, "job %d: null device pointer", i);
@@ -959,10 +978,9 @@ int capture_graph(BatchState &b) {
 
 // Frees the batch states whose jobs use this plan (their keys list the
 // pattern ids as "id:RxC;"), after the work in flight has completed.
-void drop_batches_of(int pattern_id) {
-    const std::string pref = std::to_string(pattern_id) + ":";
-    bool synced = false;
-    for (auto it = g_batches.begin(); it != g_batches.end();) {
+template <typename M>
+void drop_keyed(M &states, const std::string &pref, bool &synced) {
+    for (auto it = states.begin(); it != states.end();) {
         const std::string &k = it->first;
         const bool uses = k.compare(0, pref.size(), pref) == 0 || k.find(";" + pref) != std::string::npos;
         if (!uses) {
@@ -973,8 +991,15 @@ void drop_batches_of(int pattern_id) {
             (void)hipDeviceSynchronize();
             synced = true;
         }
-        it = g_batches.erase(it);
+        it = states.erase(it);
     }
+}
+
+void drop_batches_of(int pattern_id) {
+    const std::string pref = std::to_string(pattern_id) + ":";
+    bool synced = false;
+    drop_keyed(g_batches, pref, synced);
+    drop_keyed(g_dense_batches, pref, synced);
 }
 
 int run_batch(const ljsde_job *jobs, int n, void *stream) {
@@ -1058,8 +1083,9 @@ int ljsde_plan(const uint8_t *pattern, int pat_rows, int pat_cols, int window, i
     if (flags & ~known) return fail(LJSDE_EINVAL, "unknown flags 0x%x", flags & ~known);
     if (((flags & LJSDE_FP64) != 0) == ((flags & LJSDE_FP32) != 0))
         return fail(LJSDE_EINVAL, "exactly one of LJSDE_FP64 / LJSDE_FP32 is required");
-    if ((flags & LJSDE_PLAIN_L) && (!(flags & LJSDE_FP64) || (flags & LJSDE_DENSE_C)))
-        return fail(LJSDE_EINVAL, "LJSDE_PLAIN_L needs LJSDE_FP64 and excludes LJSDE_DENSE_C");
+    if ((flags & LJSDE_PLAIN_L) && (flags & (LJSDE_DENSE_C | LJSDE_DFT_SPLITBF16 | LJSDE_STATE_FP32)))
+        return fail(LJSDE_EINVAL,
+                    "LJSDE_PLAIN_L excludes LJSDE_DENSE_C, LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32");
     if ((flags & (LJSDE_DFT_SPLITBF16 | LJSDE_STATE_FP32)) && (flags & LJSDE_FP64))
         return fail(LJSDE_EINVAL, "LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32 apply to FP32 plans only");
     if ((flags & LJSDE_DENSE_C) && (flags & (LJSDE_DFT_SPLITBF16 | LJSDE_STATE_FP32)))
@@ -1135,8 +1161,9 @@ int ljsde_plan_weights(const double *weights, int pat_rows, int pat_cols, int wi
     if (!(block == 4 || block == 8))
         return fail(LJSDE_EUNSUPPORTED, "no kernel for block %d (have 4, 8)", block);
     if (iters > 32767) return fail(LJSDE_EUNSUPPORTED, "iters %d above 32767", iters);
-    if ((flags & LJSDE_PLAIN_L) && (!(flags & LJSDE_FP64) || (flags & LJSDE_DENSE_C)))
-        return fail(LJSDE_EINVAL, "LJSDE_PLAIN_L needs LJSDE_FP64 and excludes LJSDE_DENSE_C");
+    if ((flags & LJSDE_PLAIN_L) && (flags & (LJSDE_DENSE_C | LJSDE_DFT_SPLITBF16 | LJSDE_STATE_FP32)))
+        return fail(LJSDE_EINVAL,
+                    "LJSDE_PLAIN_L excludes LJSDE_DENSE_C, LJSDE_DFT_SPLITBF16 and LJSDE_STATE_FP32");
     if (!(flags & (LJSDE_DENSE_C | LJSDE_PLAIN_L)))
         return fail(LJSDE_EUNSUPPORTED,
                     "general layouts run on the dense form (LJSDE_DENSE_C) or plain L-JSDE (LJSDE_PLAIN_L) only");
@@ -1226,6 +1253,114 @@ static int ensure_dense(Plan &p, SizeSet &s, void *stream) {
     }
     s.d_dense = c;
     return LJSDE_OK;
+}
+
+// One launch of the dense form over the windows of many images (plans of
+// the dense form with equal window, block, iterations, rho, gamma, energy
+// floor, pixel shape and output type). Windows are sorted by class inside
+// each image, the images' lists concatenated and cut into XCD_RANGES chunks
+// as for one image (workgroup b runs entry b / XCD_RANGES of chunk
+// b % XCD_RANGES), so an XCD works through the classes of a few images.
+static int run_dense_batch(const ljsde_job *jobs, int n, void *stream) {
+    Plan *p0 = nullptr;
+    int st = get_plan(jobs[0].pattern_id, &p0);
+    if (st) return st;
+    std::ostringstream key;
+    for (int i = 0; i < n; ++i) {
+        Plan *p = nullptr;
+        st = get_plan(jobs[i].pattern_id, &p);
+        if (st) return st;
+        if (!(p->flags & LJSDE_DENSE_C))
+            return fail(LJSDE_EINVAL, "job %d: a batch of the dense form needs dense-form plans only", i);
+        if (p->W != p0->W || p->B != p0->B || p->iters != p0->iters || p->gamma != p0->gamma ||
+            p->rho != p0->rho || p->tau != p0->tau || p->shape != p0->shape || p->fp64() != p0->fp64())
+            return fail(LJSDE_EINVAL, "job %d: all plans of a dense batch need equal window, block, iters, rho, "
+                                      "gamma, energy floor, pixel shape and precision", i);
+        if (!jobs[i].measurements || !jobs[i].out) return fail(LJSDE_EINVAL, "job %d: null device pointer", i);
+        st = check_size(*p, jobs[i].sensor_rows, jobs[i].sensor_cols);
+        if (st) return st;
+        key << jobs[i].pattern_id << ':' << jobs[i].sensor_rows << 'x' << jobs[i].sensor_cols << ';';
+    }
+    int dev = 0;
+    st = current_device(&dev);
+    if (st) return st;
+    key << "@" << dev << "/s" << (uintptr_t)stream;
+    auto &slot = g_dense_batches[key.str()];
+    if (!slot) {
+        auto b = std::make_unique<DenseBatch>();
+        std::vector<int> list;  // (job, window) pairs
+        for (int i = 0; i < n; ++i) {
+            Plan *p = nullptr;
+            get_plan(jobs[i].pattern_id, &p);
+            SizeSet *sz = nullptr;
+            if ((st = get_size(*p, jobs[i].sensor_rows, jobs[i].sensor_cols, &sz)) || (st = ensure_device(*p, *sz)) ||
+                (st = ensure_dense(*p, *sz, stream))) {
+                g_dense_batches.erase(key.str());
+                return st;
+            }
+            KJob j = make_job(*p, *sz, nullptr, nullptr, nullptr, 0);
+            j.dense = sz->d_dense;
+            b->host_jobs.push_back(j);
+            const int nw = sz->nbi * sz->nbj, nck = (int)sz->colkeys.size();
+            std::vector<int> win(nw);
+            for (int w = 0; w < nw; ++w) win[w] = w;
+            std::stable_sort(win.begin(), win.end(), [&](int a, int c) {
+                return sz->rowcls[a / sz->nbj] * nck + sz->colcls[a % sz->nbj] <
+                       sz->rowcls[c / sz->nbj] * nck + sz->colcls[c % sz->nbj];
+            });
+            for (int w : win) {
+                list.push_back(i);
+                list.push_back(w);
+            }
+        }
+        const int total = (int)(list.size() / 2);
+        const int cs = (total + XCD_RANGES - 1) / XCD_RANGES;
+        std::vector<int> order((size_t)cs * XCD_RANGES * 2, -1);
+        for (int x = 0; x < XCD_RANGES; ++x)
+            for (int i = 0; i < cs && x * cs + i < total; ++i) {
+                order[((size_t)i * XCD_RANGES + x) * 2] = list[(size_t)(x * cs + i) * 2];
+                order[((size_t)i * XCD_RANGES + x) * 2 + 1] = list[(size_t)(x * cs + i) * 2 + 1];
+            }
+        b->n_order = cs * XCD_RANGES;
+        b->params = make_params(*p0);
+        b->ws = p0->Ws;
+        b->f32io = !p0->fp64();
+        if ((st = dev_alloc((void **)&b->d_jobs, sizeof(KJob) * n)) ||
+            (st = dev_alloc((void **)&b->d_order, sizeof(int) * std::max<size_t>(order.size(), 2)))) {
+            g_dense_batches.erase(key.str());
+            return st;
+        }
+        const hipError_t e = hipMemcpy(b->d_order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            g_dense_batches.erase(key.str());
+            return fail(LJSDE_EHIP, "dense batch order upload: %s", hipGetErrorString(e));
+        }
+        slot = std::move(b);
+    }
+    DenseBatch *b = slot.get();
+    bool changed = false;
+    for (int i = 0; i < n; ++i) {
+        KJob &j = b->host_jobs[i];
+        if (j.y != jobs[i].measurements || j.out != jobs[i].out) {
+            j.y = jobs[i].measurements;
+            j.out = jobs[i].out;
+            changed = true;
+        }
+    }
+    if (changed) {
+        for (int i = 0; i < n; ++i) {
+            if ((st = check_device_buffer(jobs[i].measurements, "measurements", i)) ||
+                (st = check_device_buffer(jobs[i].out, "out", i))) {
+                for (int k = 0; k < n; ++k) b->host_jobs[k].y = b->host_jobs[k].out = nullptr;  // re-check next call
+                return st;
+            }
+        }
+        if (stream) HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+        HIP_TRY(hipMemcpy(b->d_jobs, b->host_jobs.data(), sizeof(KJob) * n, hipMemcpyHostToDevice));
+    }
+    const int e = launch_dense_batch(b->params, b->d_jobs, b->d_order, b->n_order, b->ws, b->f32io, stream);
+    if (e) return fail(LJSDE_EHIP, "dense batch launch: %s", hipGetErrorString((hipError_t)e));
+    return ok();
 }
 
 // Window groups of plain L-JSDE: windows sorted by class (row-major inside
@@ -1319,7 +1454,7 @@ static int reconstruct_impl(const void *y, int Ms, int Ns, int id, void *out, in
     if (p->flags & LJSDE_PLAIN_L) {
         st = ensure_lplain(*p, *s, stream);
         if (st) return st;
-        e = launch_lplain(k, j, s->d_la, s->d_laux, s->d_lgroups, s->n_lgroups, p->Ws, stream);
+        e = launch_lplain(k, j, s->d_la, s->d_laux, s->d_lgroups, s->n_lgroups, p->Ws, !p->fp64(), stream);
     } else if (p->flags & LJSDE_DENSE_C) {
         st = ensure_dense(*p, *s, stream);
         if (st) return st;
@@ -1350,6 +1485,12 @@ int ljsde_reconstruct_diag(const void *measurements, int sensor_rows, int sensor
 
 int ljsde_reconstruct_batch(const ljsde_job *jobs, int n_jobs, void *stream) {
     std::lock_guard<std::mutex> lk(g_mu);
+    if (jobs && n_jobs > 0) {
+        Plan *p0 = nullptr;
+        const int st = get_plan(jobs[0].pattern_id, &p0);
+        if (st) return st;
+        if (p0->flags & LJSDE_DENSE_C) return run_dense_batch(jobs, n_jobs, stream);
+    }
     return run_batch(jobs, n_jobs, stream);
 }
 
@@ -1363,9 +1504,9 @@ int ljsde_reconstruct_noalloc(const void *measurements, int sensor_rows, int sen
     Plan *p = nullptr;
     int st = get_plan(pattern_id, &p);
     if (st) return st;
-    if (p->fp64() || (p->flags & (LJSDE_DENSE_C | LJSDE_STATE_FP32)))
+    if (p->fp64() || (p->flags & (LJSDE_DENSE_C | LJSDE_STATE_FP32 | LJSDE_PLAIN_L)))
         return fail(LJSDE_EUNSUPPORTED, "ljsde_reconstruct_noalloc needs an FP32 plan of the factorised form "
-                                        "(not LJSDE_FP64, LJSDE_DENSE_C or LJSDE_STATE_FP32)");
+                                        "(not LJSDE_FP64, LJSDE_DENSE_C, LJSDE_STATE_FP32 or LJSDE_PLAIN_L)");
     if (!measurements || !out) return fail(LJSDE_EINVAL, "null device pointer");
     st = check_size(*p, sensor_rows, sensor_cols);
     if (st) return st;

@@ -60,6 +60,7 @@ struct KJob {
     int y64;                       // measurements are double (FP64 plans, and FP32 plans
                                    // made with LJSDE_INPUT_F64), else float
     long long win_begin;           // first global window index of this job
+    const void *dense;             // dense C of the job's size set (batched dense form), else null
 };
 
 // Up to four windows of one job that share a class (persistent FP32 path).
@@ -122,8 +123,13 @@ size_t lplain_aux_bytes(int ws, int n_classes);
 // of eq. (10) with q/D and 1/D for every class of a size set.
 int launch_lplain_build(const KParams &p, const unsigned char *tables, int n_classes, int ws, void *a, void *aux,
                         void *stream);
+// Batched dense form: `order` is int2 [n] = (job, window) per workgroup
+// (job < 0: idle); every job carries its dense C in KJob::dense.
+int launch_dense_batch(const KParams &p, const KJob *jobs, const void *order, int n, int ws, bool f32io,
+                       void *stream);
+// f32io: float output (FP32 plans; FP64 arithmetic), else double.
 int launch_lplain(const KParams &p, const KJob &job, const void *a, const void *aux, const LGroup *groups,
-                  int ngroups, int ws, void *stream);
+                  int ngroups, int ws, bool f32io, void *stream);
 
 // Allocation-free single-image launch of the persistent FP32 kernel. Its work
 // memory (counters, group ranges, the job and the window groups) is a

@@ -171,7 +171,9 @@ struct LStep {
 };
 
 // One workgroup (4 wavefronts) per group of up to LGROUP windows of one class.
-template <int WS>
+// IO is the element type of the output (FP32 plans: float; the arithmetic is
+// FP64 either way); the measurements are double or float by the job's flag.
+template <int WS, typename IO>
 __global__ __launch_bounds__(256) void lplain_kernel(KParams p, KJob j, const double2 *__restrict__ amat,
                                                      const double *__restrict__ aux,
                                                      const LGroup *__restrict__ groups) {
@@ -345,7 +347,7 @@ __global__ __launch_bounds__(256) void lplain_kernel(KParams p, KJob j, const do
             const int w = e / p.iters, nu = e % p.iters;
             if (nu >= nu_done) j.sel[(size_t)groups[blockIdx.x].win[w] * p.iters + nu] = -1;
         }
-    double *O = (double *)j.out;
+    IO *O = (IO *)j.out;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int e = tid + 256 * q;
@@ -353,7 +355,7 @@ __global__ __launch_bounds__(256) void lplain_kernel(KParams p, KJob j, const do
             const int w = groups[blockIdx.x].win[e / BB];
             const int bi = w / j.nbj, bj = w % j.nbj;
             const int px = e % BB, oi = px / p.B, oj = px % p.B;
-            O[(size_t)(p.B * bi + oi) * (size_t)(2 * j.Ns) + (size_t)(p.B * bj + oj)] = outacc[q];
+            O[(size_t)(p.B * bi + oi) * (size_t)(2 * j.Ns) + (size_t)(p.B * bj + oj)] = (IO)outacc[q];
         }
     }
 }
@@ -377,16 +379,23 @@ int launch_lplain_build(const KParams &p, const unsigned char *tables, int n_cla
                     : launch_build<8>(p, tables, n_classes, a, aux, stream);
 }
 
-int launch_lplain(const KParams &p, const KJob &job, const void *a, const void *aux, const LGroup *groups,
-                  int ngroups, int ws, void *stream) {
-    if (ngroups <= 0) return 0;
+template <typename IO>
+static int launch_lplain_io(const KParams &p, const KJob &job, const void *a, const void *aux, const LGroup *groups,
+                            int ngroups, int ws, void *stream) {
     if (ws == 16)
-        lplain_kernel<16><<<dim3(ngroups), dim3(256), 0, (hipStream_t)stream>>>(p, job, (const double2 *)a,
-                                                                               (const double *)aux, groups);
+        lplain_kernel<16, IO><<<dim3(ngroups), dim3(256), 0, (hipStream_t)stream>>>(p, job, (const double2 *)a,
+                                                                                   (const double *)aux, groups);
     else
-        lplain_kernel<8><<<dim3(ngroups), dim3(256), 0, (hipStream_t)stream>>>(p, job, (const double2 *)a,
-                                                                              (const double *)aux, groups);
+        lplain_kernel<8, IO><<<dim3(ngroups), dim3(256), 0, (hipStream_t)stream>>>(p, job, (const double2 *)a,
+                                                                                  (const double *)aux, groups);
     return (int)hipGetLastError();
+}
+
+int launch_lplain(const KParams &p, const KJob &job, const void *a, const void *aux, const LGroup *groups,
+                  int ngroups, int ws, bool f32io, void *stream) {
+    if (ngroups <= 0) return 0;
+    return f32io ? launch_lplain_io<float>(p, job, a, aux, groups, ngroups, ws, stream)
+                 : launch_lplain_io<double>(p, job, a, aux, groups, ngroups, ws, stream);
 }
 
 }  // namespace ljsde

@@ -37,7 +37,7 @@ STATE_FP32 = 16
 DENSE_C = 32
 WEIGHTS = 64  # reported by plan_info for plans of plan_weights
 INPUT_F64 = 128  # FP32 plans: double measurements (float output)
-PLAIN_L = 4096  # FP64 plans: plain L-JSDE (residual in the measurement domain, eq. (10) every iteration)
+PLAIN_L = 4096  # plain L-JSDE (residual in the measurement domain, eq. (10) every iteration; FP64 arithmetic)
 
 _NAMES = {EINVAL: "EINVAL", EUNSUPPORTED: "EUNSUPPORTED", ENOMEM: "ENOMEM", EHIP: "EHIP", EBADID: "EBADID"}
 
@@ -116,8 +116,9 @@ def plan(pattern, window: int = 32, block: int = 4, iters: int = 100, rho: float
     selects the dense form (FP64 arithmetic; float32 I/O for FP32 plans): per
     class the full C of eq. (14) in device memory, R as the loop state.
     ``input_f64``: an FP32 plan that takes float64 measurements (the output
-    stays float32). ``plain_l`` (with ``fp64``): plain L-JSDE, the residual
-    kept in the measurement domain and eq. (10) evaluated densely."""
+    stays float32). ``plain_l``: plain L-JSDE, the residual kept in the
+    measurement domain and eq. (10) evaluated densely (FP64 arithmetic; FP32
+    plans take float32 I/O)."""
     pat = np.ascontiguousarray(np.asarray(pattern, dtype=np.uint8))
     if pat.ndim != 2:
         raise ValueError("pattern must be 2-D")
@@ -135,8 +136,7 @@ def plan_weights(weights, window: int = 32, block: int = 4, iters: int = 100, rh
     tile of per-pixel quadrant weights (quadrant 2a + b of the footprint).
     Runs on the dense form in FP64; ``fp64=False`` takes float32
     measurements and returns float32 images (float64 measurements with
-    ``input_f64``). ``plain_l``: plain L-JSDE instead of the dense form
-    (FP64 only)."""
+    ``input_f64``). ``plain_l``: plain L-JSDE instead of the dense form."""
     wt = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
     if wt.ndim != 3 or wt.shape[2] != 4:
         raise ValueError("weights must be a [rows, cols, 4] tile")
@@ -247,7 +247,8 @@ def _jobs(items: Sequence) -> ctypes.Array:
 
 def reconstruct_batch(items: Iterable, stream=None) -> None:
     """``items``: sequence of (y, plan_id, out) device tensors of FP32 plans
-    (y float32, or float64 for plans with ``input_f64``; out float32)."""
+    (y float32, or float64 for plans with ``input_f64``; out float32), or of
+    plans of the dense form (one launch of the dense form over all images)."""
     import torch
     items = list(items)
     _check_items(items)
@@ -258,8 +259,10 @@ def reconstruct_batch(items: Iterable, stream=None) -> None:
 def _check_items(items):
     import torch
     for y, pid, out in items:
-        if plan_info(pid)["flags"] & FP64:
-            raise TypeError(f"plan {pid} is an FP64 plan: batches take FP32 plans")
+        flags = plan_info(pid)["flags"]
+        if flags & FP64 and not flags & DENSE_C:
+            raise TypeError(f"plan {pid} is an FP64 plan of the factorised form: batches take FP32 plans "
+                            "or plans of the dense form")
         ydt, odt = _dtypes(pid)
         _as_input(y, ydt)
         _check_out(y, out, odt)

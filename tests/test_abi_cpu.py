@@ -271,10 +271,12 @@ def test_class_tables_reproduce_dense_C_and_D(W, bi, bj, shape):
     ljsde.release(pid)
 
 
-@pytest.mark.parametrize("other", [dict(shape=ljsde.SHAPE_QUARTER), dict(splitbf16=True), dict(iters=11)])
+@pytest.mark.parametrize("other", [dict(shape=ljsde.SHAPE_QUARTER), dict(splitbf16=True), dict(iters=11),
+                                   dict(rho=0.6)])
 def test_batch_rejects_plans_that_need_another_kernel(other):
-    """All plans of one batched launch run in one kernel instantiation, so a
-    batch that mixes pixel shapes, DFT modes or iteration counts is refused on
+    """All plans of one batched launch run in one kernel instantiation with
+    the first plan's class-independent tables, so a batch that mixes pixel
+    shapes, DFT modes, iteration counts or spatial weights (rho) is refused on
     the host (before any device work)."""
     base = dict(iters=10)
     p0 = ljsde.plan(TILE, **base)
@@ -434,16 +436,10 @@ def test_two_and_four_quadrant_masks_run_as_weights_plans(mask):
     ljsde.release(pid)
 
 
-@pytest.mark.parametrize("kind", ["fp64", "weights", "half_pixels"])
-def test_batch_refuses_plans_without_a_batched_kernel(kind):
-    """Batched launches run the FP32 persistent kernel: FP64 plans, general
-    layouts and half/full pixels (dense FP64 form) are refused on the host."""
-    if kind == "fp64":
-        pid = ljsde.plan(TILE, iters=10, fp64=True)
-    elif kind == "weights":
-        pid = ljsde.plan_weights(WTILE, iters=10)
-    else:
-        pid = ljsde.plan(TILE, iters=10, fp64=True, dense_c=True, shape=0x3)
+def test_batch_refuses_plans_without_a_batched_kernel():
+    """Batched launches run the FP32 persistent kernel or the dense form: FP64
+    plans of the factorised form are refused on the host."""
+    pid = ljsde.plan(TILE, iters=10, fp64=True)
     buf = (ctypes.c_double * 64)()
     addr = ctypes.cast(buf, ctypes.c_void_p).value
     jobs = (ljsde.Job * 1)(ljsde.Job(addr, 4, 4, pid, addr))
@@ -452,19 +448,34 @@ def test_batch_refuses_plans_without_a_batched_kernel(kind):
     ljsde.release(pid)
 
 
-def test_fp32_dense_plans_are_accepted_and_not_batched():
+@pytest.mark.parametrize("other", [dict(dense_c=False), dict(dense_c=True, rho=0.6), dict(dense_c=True, iters=11),
+                                   dict(dense_c=True, fp64=False), dict(dense_c=True, shape=0x1)])
+def test_dense_batch_refuses_mixed_plans(other):
+    """A batch whose first plan is of the dense form runs the batched dense
+    kernel: every plan must be of the dense form with equal window, block,
+    iterations, rho, gamma, energy floor, pixel shape and precision (checked
+    on the host, before any device work)."""
+    p0 = ljsde.plan(TILE, iters=10, fp64=True, dense_c=True)
+    kw = dict(iters=10, fp64=True)
+    kw.update(other)
+    p1 = ljsde.plan(TILE, **kw)
+    buf = (ctypes.c_double * 64)()
+    addr = ctypes.cast(buf, ctypes.c_void_p).value
+    jobs = (ljsde.Job * 2)(ljsde.Job(addr, 4, 4, p0, addr), ljsde.Job(addr, 4, 4, p1, addr))
+    assert ljsde.lib().ljsde_reconstruct_batch(jobs, 2, None) == ljsde.EINVAL
+    assert "job 1" in ljsde.last_error()
+    ljsde.release(p0)
+    ljsde.release(p1)
+
+
+def test_fp32_dense_plans_are_accepted():
     """FP32 plans of the dense form (float I/O, FP64 arithmetic), for codes,
-    half pixels and general layouts; batched launches refuse them."""
+    half pixels and general layouts."""
     pids = [ljsde.plan(TILE, iters=10, dense_c=True), ljsde.plan(TILE, iters=10, dense_c=True, shape=0x3),
             ljsde.plan_weights(WTILE, iters=10, fp64=False)]
     for pid in pids:
         f = ljsde.plan_info(pid)["flags"]
         assert f & ljsde.FP32 and f & ljsde.DENSE_C
-        buf = (ctypes.c_float * 64)()
-        addr = ctypes.cast(buf, ctypes.c_void_p).value
-        jobs = (ljsde.Job * 1)(ljsde.Job(addr, 4, 4, pid, addr))
-        assert ljsde.lib().ljsde_reconstruct_batch(jobs, 1, None) == ljsde.EUNSUPPORTED
-        assert "factorised" in ljsde.last_error()
         ljsde.release(pid)
 
 
@@ -500,12 +511,18 @@ def test_noalloc_refusals_are_host_side():
 
 
 def test_plain_l_flag_validation():
-    """LJSDE_PLAIN_L: FP64 plans only, not with the dense form; it lets two-
-    and four-quadrant masks and general layouts run without LJSDE_DENSE_C."""
+    """LJSDE_PLAIN_L: FP64 plans, or FP32 plans (float I/O, FP64 arithmetic);
+    not with the dense form, the split-BF16 DFT or the all-FP32 state; it lets
+    two- and four-quadrant masks and general layouts run without
+    LJSDE_DENSE_C. FP32 plain L-JSDE plans are neither batched nor taken by
+    the allocation-free call."""
     assert ljsde.plan(TILE, iters=5, fp64=True, plain_l=True) >= 0
-    with pytest.raises(ljsde.LjsdeError) as e:
-        ljsde.plan(TILE, iters=5, fp64=False, plain_l=True)
-    assert e.value.code == ljsde.EINVAL
+    p32 = ljsde.plan(TILE, iters=5, plain_l=True)
+    assert ljsde.plan_info(p32)["flags"] & ljsde.PLAIN_L
+    for bad in (dict(dense_c=True), dict(splitbf16=True), dict(state_fp32=True)):
+        with pytest.raises(ljsde.LjsdeError) as e:
+            ljsde.plan(TILE, iters=5, plain_l=True, **bad)
+        assert e.value.code == ljsde.EINVAL
     with pytest.raises(ljsde.LjsdeError) as e:
         ljsde.plan(TILE, iters=5, fp64=True, plain_l=True, dense_c=True)
     assert e.value.code == ljsde.EINVAL
@@ -515,6 +532,14 @@ def test_plain_l_flag_validation():
     wt = random_weights(2, 2, seed=1)
     pw = ljsde.plan_weights(wt, iters=5, plain_l=True)
     assert ljsde.plan_info(pw)["flags"] & ljsde.PLAIN_L
-    with pytest.raises(ljsde.LjsdeError) as e:
-        ljsde.plan_weights(wt, iters=5, plain_l=True, fp64=False)
-    assert e.value.code == ljsde.EINVAL
+    pw32 = ljsde.plan_weights(wt, iters=5, plain_l=True, fp64=False)
+    assert ljsde.plan_info(pw32)["flags"] & ljsde.FP32
+    # the FP32 plain L-JSDE plan has no batched or allocation-free kernel
+    buf = (ctypes.c_double * 64)()
+    addr = ctypes.cast(buf, ctypes.c_void_p).value
+    jobs = (ljsde.Job * 1)(ljsde.Job(addr, 4, 4, p32, addr))
+    assert ljsde.lib().ljsde_reconstruct_batch(jobs, 1, None) == ljsde.EUNSUPPORTED
+    assert ljsde.lib().ljsde_reconstruct_noalloc(ctypes.c_void_p(addr), 4, 4, p32, ctypes.c_void_p(addr),
+                                                 None) == ljsde.EUNSUPPORTED
+    for q in (p32, pid, pw, pw32):
+        ljsde.release(q)

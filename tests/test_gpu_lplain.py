@@ -132,3 +132,26 @@ def test_plain_l_equals_recurrent_fp64_on_every_window(L):
     assert torch.equal(sl, sr)
     L.release(pl)
     L.release(pr)
+
+
+@pytest.mark.parametrize("input_f64", [True, False], ids=["f64in", "f32in"])
+def test_plain_l_fp32_plans_match_oracle(L, input_f64):
+    """FP32 plans of plain L-JSDE: float output (and float32 measurements
+    unless input_f64), FP64 arithmetic. Against the oracle's literal L form on
+    the same measurements: equal selection sequences, and the output within
+    its float32 rounding."""
+    c = make_case(48, 40, 4, seed=21)
+    y = c["y"] if input_f64 else c["y"].astype(np.float32).astype(np.float64)
+    ref, tr = O.reconstruct(y, c["tile"], W=32, B=4, iters=30, form="L", traces=True)
+    pid = L.plan(c["tile"], iters=30, plain_l=True, input_f64=input_f64)
+    yd = torch.from_numpy(np.ascontiguousarray(y, dtype=np.float64 if input_f64 else np.float32)).to("cuda:0")
+    out, sel = L.reconstruct_diag(yd, pid)
+    assert out.dtype == torch.float32
+    out, sel = out.cpu().numpy().astype(np.float64), sel.cpu().numpy()
+    err = float(np.max(np.abs(out - ref)))
+    print(f"plain L-JSDE FP32 plan ({'float64' if input_f64 else 'float32'} input): max-abs {err:.3e}")
+    assert err <= 1e-4
+    nbj = out.shape[1] // 4
+    for w in range(sel.shape[0]):
+        assert list(sel[w]) == tr[divmod(w, nbj)].picks, w
+    L.release(pid)

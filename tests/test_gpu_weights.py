@@ -230,3 +230,39 @@ def test_fp32_dense_plans_match_oracle_on_float32_input(L, kind, name):
     assert out.dtype == torch.float32
     _check(out, sel, ref, tr, B, 1e-4, f"{name} FP32 dense")
     L.release(pid)
+
+
+@pytest.mark.parametrize("kind", ["fp64", "fp32_io", "general"])
+def test_dense_batch_equals_single_image_calls(L, kind):
+    """The dense form over many images in one launch (ljsde_reconstruct_batch
+    with dense-form plans): every image equals its single-image dense call
+    bitwise, on two consecutive batch calls (the second reuses the batch's
+    job table and launch order with new output buffers)."""
+    from synth import make_case
+    shapes = [(48, 40, 4), (32, 56, 2), (40, 40, (3, 5))]
+    items, singles = [], []
+    for k, (r, cc, per) in enumerate(shapes):
+        if kind == "general":
+            wt = random_weights(4, 4, seed=50 + k)
+            _, obs = synthetic_image(r, cc, seed=60 + k)
+            y = sense_weights(obs, wt)
+            pid = L.plan_weights(wt, iters=25)
+            ydt, odt = torch.float64, torch.float64
+        else:
+            c = make_case(r, cc, per, seed=70 + k)
+            y = c["y"]
+            pid = L.plan(c["tile"], iters=25, fp64=(kind == "fp64"), dense_c=True, input_f64=(kind == "fp32_io"))
+            ydt, odt = torch.float64, (torch.float64 if kind == "fp64" else torch.float32)
+        yd = torch.from_numpy(np.ascontiguousarray(y)).to("cuda:0").to(ydt)
+        items.append((yd, pid, torch.full((r, cc), float("nan"), dtype=odt, device="cuda:0")))
+        singles.append(L.reconstruct(yd, pid).clone())
+    print(f"dense batch ({kind})", flush=True)
+    for rep in range(2):
+        if rep:
+            items = [(y, pid, torch.full_like(o, float("nan"))) for y, pid, o in items]
+        L.reconstruct_batch(items)
+        torch.cuda.synchronize()
+        for (_, _, o), s in zip(items, singles):
+            assert torch.equal(o, s), rep
+    for _, pid, _ in items:
+        L.release(pid)
