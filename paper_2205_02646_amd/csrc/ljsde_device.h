@@ -103,7 +103,14 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
     v = max(v, dpp_u32<DPP_ROW_MIRROR>(v));
     const unsigned r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
     const unsigned r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
-    return max(max(r0, r1), max(r2, r3));
+    // the four row maxima are scalars: reduce them on the scalar unit (left
+    // to itself the compiler forms a vector max3 and copies two of them into
+    // vector registers for it)
+    unsigned m01, m23, m;
+    asm("s_max_u32 %0, %1, %2" : "=s"(m01) : "s"(r0), "s"(r1));
+    asm("s_max_u32 %0, %1, %2" : "=s"(m23) : "s"(r2), "s"(r3));
+    asm("s_max_u32 %0, %1, %2" : "=s"(m) : "s"(m01), "s"(m23));
+    return m;
 }
 
 // Selection ties (eqs. (10)-(11)): metrics within a relative TIE_REL of the

@@ -31,6 +31,28 @@ typedef const double __attribute__((address_space(4))) CDouble;
 // holds up the waits on LDS reads.
 typedef int16_t __attribute__((address_space(1))) GInt16;
 
+// R(a, b) of one position in FP32: the same linear map as project4, with
+// the per-quadrant sums of three-quarter sampling taken from two pair sums
+// (each Q_q adds the three orientations other than q: 12 operations instead
+// of 14). Folding the twiddle products into the Walsh-Hadamard additions as
+// fused multiply-adds (with the differences taken as 2 x - s) saves 4 more
+// operations per position but runs slower on gfx950: the three-operand
+// instructions and the longer dependency chains cost more than the additions
+// they replace.
+template <int SHAPE>
+__device__ __forceinline__ void project4_f32(const C2<float> P[4], C2<float> tl, C2<float> tk, C2<float> tkl,
+                                             C2<float> R[4]) {
+    if constexpr (SHAPE == SHAPE_THREE_QUARTER) {
+        const C2<float> a = {P[0].re + P[1].re, P[0].im + P[1].im};
+        const C2<float> b = {P[2].re + P[3].re, P[2].im + P[3].im};
+        const C2<float> Q[4] = {{P[1].re + b.re, P[1].im + b.im}, {P[0].re + b.re, P[0].im + b.im},
+                                {a.re + P[3].re, a.im + P[3].im}, {a.re + P[2].re, a.im + P[2].im}};
+        project4<float, SHAPE_QUARTER>(Q, tl, tk, tkl, R);  // the twiddled 2 x 2 step on Q
+    } else {
+        project4<float, SHAPE>(P, tl, tk, tkl, R);
+    }
+}
+
 template <int WS>
 struct MixedLds {
     static constexpr int NPOS = WS * WS;
@@ -203,7 +225,7 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
             C2<float> Pf[4], R[4];
 #pragma unroll
             for (int o = 0; o < 4; ++o) Pf[o] = {(float)P[t][o].re, (float)P[t][o].im};
-            project4<float, SHAPE>(Pf, tl, C2<float>{t4.x, t4.y}, C2<float>{t4.z, t4.w}, R);
+            project4_f32<SHAPE>(Pf, tl, C2<float>{t4.x, t4.y}, C2<float>{t4.z, t4.w}, R);
             const float qd[4] = {q4.x, q4.y, q4.z, q4.w};
             unsigned key[4];
 #pragma unroll

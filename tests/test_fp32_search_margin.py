@@ -9,9 +9,12 @@ in FP64). This test replays that arithmetic on the CPU: an FP64 recurrent loop
 in the factorised form (its selection sequences are checked against the
 oracle's), and at every iteration the FP32 evaluation of all W^2 metrics from
 the FP64 state, in the kernel's order of operations (rounding of P to float32,
-the per-quadrant sums, the twiddle products, the 2 x 2 Walsh-Hadamard step,
-|R|^2 q / D with q / D rounded to float32, the four low bits of the key
-replaced by the frequency code). It asserts that every accepted FP32 decision
+the per-quadrant sums from two pair sums, the twiddle products with the
+compiler's contraction (re = fma(t_re, q_re, -(t_im q_im)), im = fma(t_re,
+q_im, t_im q_re)), the 2 x 2 Walsh-Hadamard step, |R|^2 q / D with q / D
+rounded to float32, the four low bits of the key replaced by the frequency
+code). A fused multiply-add is replayed as the exact product and sum in
+float64, rounded once more to float32. It asserts that every accepted FP32 decision
 equals the FP64 decision, and measures the largest FP32 metric error relative
 to the maximum metric among the candidates within 1e-3 of it: the guard's
 margin is 1e-4 divided by twice that error.
@@ -43,13 +46,19 @@ def _fp32_keys(P, qd32, shape):
     """FP32 metrics (as keys with the 4 low bits cleared) of all W^2
     frequencies from the FP64 state P [4][WS][WS], in the kernel's order."""
     f32 = np.float32
+    f64 = np.float64
+
+    def fma(x, y, z):
+        return (np.asarray(x, f64) * np.asarray(y, f64) + np.asarray(z, f64)).astype(f32)
+
     Pr = P.real.astype(f32)
     Pi = P.imag.astype(f32)
     if shape == THREE_QUARTER:
-        spr = ((Pr[0] + Pr[1]) + Pr[2]) + Pr[3]
-        spi = ((Pi[0] + Pi[1]) + Pi[2]) + Pi[3]
-        Qr = [spr - Pr[q] for q in range(4)]
-        Qi = [spi - Pi[q] for q in range(4)]
+        # Q_q is the sum of the three orientations other than q, from two pair sums
+        ar, ai = Pr[0] + Pr[1], Pi[0] + Pi[1]
+        br, bi = Pr[2] + Pr[3], Pi[2] + Pi[3]
+        Qr = [Pr[1] + br, Pr[0] + br, ar + Pr[3], ar + Pr[2]]
+        Qi = [Pi[1] + bi, Pi[0] + bi, ai + Pi[3], ai + Pi[2]]
     else:
         Qr = [Pr[q] for q in range(4)]
         Qi = [Pi[q] for q in range(4)]
@@ -61,8 +70,8 @@ def _fp32_keys(P, qd32, shape):
     ckl = np.cos(THETA * (k[:, None] + k[None, :])).astype(f32)
     skl = (-np.sin(THETA * (k[:, None] + k[None, :]))).astype(f32)
 
-    def cmul(ar, ai, br, bi):
-        return ar * br - ai * bi, ar * bi + ai * br
+    def cmul(tr, ti, qr, qi):
+        return fma(tr, qr, -(ti * qi)), fma(tr, qi, ti * qr)
 
     u1 = cmul(cl, sl, Qr[1], Qi[1])
     u2 = cmul(ck, sk, Qr[2], Qi[2])
@@ -76,7 +85,7 @@ def _fp32_keys(P, qd32, shape):
     keys = np.zeros((W, W), dtype=f32)
     for (a, b), (rr, ri) in R.items():
         qd = qd32[WS * a:WS * a + WS, WS * b:WS * b + WS]
-        m = (rr * rr + ri * ri) * qd
+        m = fma(rr, rr, ri * ri) * qd
         # the key keeps the metric's upper bits; the low 4 bits carry the code
         keys[WS * a:WS * a + WS, WS * b:WS * b + WS] = (m.view(np.uint32) & np.uint32(~15 & 0xFFFFFFFF)).view(f32)
     return keys.reshape(-1)
