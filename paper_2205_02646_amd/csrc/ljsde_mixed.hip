@@ -182,11 +182,34 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
     const CDouble *Ht = (const CDouble *)p.c.H;
     const CDouble *invDs = (const CDouble *)invD;
 
-    const int BB = p.B * p.B;
+    const int BB = p.B * p.B;  // 16 or 64: divides the wavefront
     const int oi = lane / p.B, oj = lane % p.B;
     double outacc = 0.0;
     double E = e0;
     int nu_done = 0;
+    // Eq. (18) over the picks kept so far (their coefficient step and
+    // frequency, in this wavefront's DFT stage, free after the prologue): lane
+    // L sums output pixel L % BB over picks L / BB, L / BB + 64 / BB, ...; the
+    // parts of a pixel are then added across the lanes BB apart.
+    C2<double> *pk = stage;
+    int *pidx = (int *)X;
+    constexpr int PCAP = NPOS;
+    int npk = 0;
+    const int xo = p.off + (lane % BB) / p.B, yo = p.off + (lane % BB) % p.B;
+    auto add_picks = [&]() {
+        wave_lds_fence();
+        double acc = 0.0;
+        for (int k = lane / BB; k < npk; k += 64 / BB) {
+            const int f = pidx[k];
+            const C2<double> g = pk[k];
+            const int ph = (xo * (f / W) + yo * (f % W)) & (W - 1);
+            acc += g.re * ew[2 * ph] - g.im * ew[2 * ph + 1];
+        }
+        for (int s = BB; s < 64; s <<= 1) acc += __shfl_xor(acc, s);
+        outacc += acc;
+        npk = 0;
+        wave_lds_fence();
+    };
     float4 q4r[QREG ? QPL : 1], t4r[QREG ? QPL : 1];
     if constexpr (QREG) {
 #pragma unroll
@@ -313,54 +336,55 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         rr = readlane_f64(rr, owner);
         ri = readlane_f64(ri, owner);
 
-        // eqs. (15)-(16) and the energy of eq. (8), FP64
+        // eqs. (15)-(16), and the energy of eq. (8) where a floor is set, FP64
         const double id = invDs[idx];
         const double gr = p.gamma * id * rr, gi = p.gamma * id * ri;
-        E = uniform_f64(E - p.ecoef * (rr * rr + ri * ri) * id);
-        // g_o = gamma delta H_o(u, v) of eq. (17) (wave-uniform, in vector
-        // registers for the update only); then the spectra of the first
-        // position of the update are read from LDS, so that their latency
+        if (p.tau > 0.0) E = uniform_f64(E - p.ecoef * (rr * rr + ri * ri) * id);
+        // the spectra of the first orientation of the update, at the lane's
+        // shifted positions, are read from LDS now, so that their latency
         // overlaps the back-transform and the stopping test
-        double gre[4], gim[4];
-#pragma unroll
-        for (int o = 0; o < 4; ++o) {
-            gre[o] = fma(gr, Hr[o], -gi * Hi[o]);
-            gim[o] = fma(gr, Hi[o], gi * Hr[o]);
-        }
         const C2<double> *Sc = (const C2<double> *)Sl + ((lam - lv) & (WS - 1));
-        C2<double> sn[4];
+        int srow[QPL];
 #pragma unroll
-        for (int o = 0; o < 4; ++o) sn[o] = Sc[o * NPOS + ((krow - ku) & (WS - 1)) * WS];
+        for (int t = 0; t < QPL; ++t) srow[t] = ((krow + KSTEP * t - ku) & (WS - 1)) * WS;
+        C2<double> sn[QPL];
+#pragma unroll
+        for (int t = 0; t < QPL; ++t) sn[t] = Sc[srow[t]];
         __builtin_amdgcn_sched_barrier(0);
-        // eq. (18) on the central block, pick by pick
-        if (lane < BB) {
-            const int ph = ((p.off + oi) * u + (p.off + oj) * v) & (W - 1);
-            outacc += gr * ew[2 * ph] - gi * ew[2 * ph + 1];
+        // eq. (18): keep the pick; the central block is summed over the kept
+        // picks when the stage is full and after the last iteration
+        if (lane == 0) {
+            pk[npk] = {gr, gi};
+            pidx[npk] = idx;
         }
+        if (++npk == PCAP) add_picks();
         if (j.sel != nullptr && lane == 0) ((GInt16 *)j.sel)[win_local * p.iters + nu] = (int16_t)idx;
         nu_done = nu + 1;
         if (p.tau > 0.0 && E <= p.tau * e0) break;
         if (nu + 1 == p.iters) break;
 
-        // eq. (17), factorised: P_o(k, l) -= g_o S_o(k - u, l - v); the
-        // spectra of position t + 1 are read while position t is updated
+        // eq. (17), factorised: P_o(k, l) -= g_o S_o(k - u, l - v) with
+        // g_o = gamma delta H_o(u, v) (wave-uniform), orientation by
+        // orientation (one coefficient live at a time); the spectra of
+        // orientation o + 1 are read while orientation o is updated
 #pragma unroll
-        for (int t = 0; t < QPL; ++t) {
-            C2<double> so[4];
+        for (int o = 0; o < 4; ++o) {
+            C2<double> so[QPL];
 #pragma unroll
-            for (int o = 0; o < 4; ++o) so[o] = sn[o];
-            if (t + 1 < QPL) {
-                const int row = (krow + KSTEP * (t + 1) - ku) & (WS - 1);
+            for (int t = 0; t < QPL; ++t) so[t] = sn[t];
+            if (o + 1 < 4) {
 #pragma unroll
-                for (int o = 0; o < 4; ++o) sn[o] = Sc[o * NPOS + row * WS];
+                for (int t = 0; t < QPL; ++t) sn[t] = Sc[(o + 1) * NPOS + srow[t]];
             }
+            const double gre = fma(gr, Hr[o], -gi * Hi[o]), gim = fma(gr, Hi[o], gi * Hr[o]);
 #pragma unroll
-            for (int o = 0; o < 4; ++o) {
-                P[t][o].re = fma(-gre[o], so[o].re, fma(gim[o], so[o].im, P[t][o].re));
-                P[t][o].im = fma(-gre[o], so[o].im, fma(-gim[o], so[o].re, P[t][o].im));
+            for (int t = 0; t < QPL; ++t) {
+                P[t][o].re = fma(-gre, so[t].re, fma(gim, so[t].im, P[t][o].re));
+                P[t][o].im = fma(-gre, so[t].im, fma(-gim, so[t].re, P[t][o].im));
             }
         }
     }
+    if (npk > 0) add_picks();
     if (j.sel != nullptr)
         for (int nu = nu_done + lane; nu < p.iters; nu += 64) j.sel[win_local * p.iters + nu] = -1;
     if (lane < BB) {
