@@ -62,6 +62,10 @@ CASES = {
     "quarter_w32b4": (48, 40, 4, 32, 4, 30, 0.7, 0.5, False, 11, QS),
     "quarter_nonrecurrent": (64, 64, None, 32, 4, 60, 0.7, 0.5, False, 12, QS),
     "quarter_w16b8": (40, 56, (3, 5), 16, 8, 30, 0.7, 0.5, False, 13, QS),
+    # more picks than the FP32 kernel keeps at once for eq. (18) (W^2 / 4:
+    # 64 at W = 16, 256 at W = 32), so its running sums are taken mid-window
+    "w16b4_long": (40, 56, (3, 5), 16, 4, 150, 0.7, 0.5, False, 17, TQ),
+    "w32b4_long": (32, 40, 4, 32, 4, 260, 0.7, 0.5, False, 18, TQ),
 }
 
 
@@ -114,6 +118,9 @@ def test_fp32_matches_oracle(L, name, state_fp32, input_f64):
     (the oracle's own input) or float32."""
     if state_fp32 and CASES[name][-1] != THREE_QUARTER:
         pytest.skip("the all-FP32 variant exists for three-quarter sampling only")
+    if state_fp32 and name.endswith("_long"):
+        pytest.skip("the FP32 state drifts over hundreds of iterations; the precision options are bounded "
+                    "at full size under a strict xfail")
     c, ref, tr, kw = _cached(name)
     if input_f64:
         y, ydt, ref_out, ref_tr = c["y"], np.float64, ref, tr
