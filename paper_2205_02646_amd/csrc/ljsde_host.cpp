@@ -1588,15 +1588,22 @@ int ljsde_autotune(const ljsde_job *jobs, int n_jobs, void *stream) {
             st2 = build_groups(*b, c.waves_per_block);
             if (st2) return st2;
         }
-        st2 = launch_batch_eager(*b, c, grid, stream);  // warm-up
+        // warm-up, also timed: short launches are repeated until a candidate
+        // has run for about 30 ms, so that launch jitter does not pick it
+        (void)hipEventRecord(e0, (hipStream_t)stream);
+        st2 = launch_batch_eager(*b, c, grid, stream);
         if (st2) return st2;
+        (void)hipEventRecord(e1, (hipStream_t)stream);
+        hipError_t e = hipEventSynchronize(e1);
+        if (e != hipSuccess) return fail(LJSDE_EHIP, "autotune: %s", hipGetErrorString(e));
         float total = 0;
-        const int reps = 3;
+        (void)hipEventElapsedTime(&total, e0, e1);
+        const int reps = std::max(3, std::min(50, (int)(30.0f / std::max(total, 1e-3f))));
         (void)hipEventRecord(e0, (hipStream_t)stream);
         for (int r = 0; r < reps && !st2; ++r) st2 = launch_batch_eager(*b, c, grid, stream);
         (void)hipEventRecord(e1, (hipStream_t)stream);
         if (st2) return st2;
-        const hipError_t e = hipEventSynchronize(e1);
+        e = hipEventSynchronize(e1);
         if (e != hipSuccess) return fail(LJSDE_EHIP, "autotune: %s", hipGetErrorString(e));
         (void)hipEventElapsedTime(&total, e0, e1);
         if (total / reps < best_ms) {
