@@ -342,7 +342,7 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         if (p.tau > 0.0) E = uniform_f64(E - p.ecoef * (rr * rr + ri * ri) * id);
         // the spectra of the first orientation of the update, at the lane's
         // shifted positions, are read from LDS now, so that their latency
-        // overlaps the back-transform and the stopping test
+        // overlaps the pick record and the stopping test
         const C2<double> *Sc = (const C2<double> *)Sl + ((lam - lv) & (WS - 1));
         int srow[QPL];
 #pragma unroll
