@@ -147,6 +147,32 @@ def test_fp32_matches_oracle(L, name, state_fp32, input_f64):
     L.release(pid)
 
 
+def test_quarter_sampling_batch_equals_single_and_graph_replays(L):
+    """The same for quarter sampling: uneven images of one pixel shape and
+    different pattern periods in one persistent launch, replayed from its graph
+    with eager work between the replays; every replay equals the single-image
+    (diagnostic-kernel) run."""
+    shapes = [(48, 40, 2), (32, 56, 4), (24, 24, 8)]
+    items, singles = [], []
+    for k, (r, cc, per) in enumerate(shapes):
+        case = make_case(r, cc, per, seed=40 + k, shape=QS)
+        pid = L.plan(case["tile"], iters=25, shape=QS, input_f64=True)
+        y = _dev(case["y"], np.float64)
+        out = torch.empty((r, cc), dtype=torch.float32, device="cuda:0")
+        items.append((y, pid, out))
+        singles.append(L.reconstruct_diag(y, pid)[0].clone())
+    for rep in range(3):
+        for _, _, out in items:
+            out.fill_(float("nan"))
+        L.reconstruct_batch(items)
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda:0").sum().item()
+        for (y, pid, out), s in zip(items, singles):
+            assert torch.equal(out, s), rep
+    for _, pid, _ in items:
+        L.release(pid)
+
+
 @pytest.mark.parametrize("state_fp32", [False, True], ids=["fp64state", "fp32state"])
 def test_batch_equals_single_and_graph_replays(L, state_fp32):
     """Uneven images, different patterns and periods, one persistent launch
