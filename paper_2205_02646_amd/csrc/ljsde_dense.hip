@@ -205,7 +205,41 @@ __device__ __forceinline__ void dense_window(const KParams &p, const KJob &j, co
 #pragma unroll
             for (int c = 0; c < 4; ++c)
                 m[t][c] = (R[t][c].re * R[t][c].re + R[t][c].im * R[t][c].im) * ldsQ[(4 * t + c) * 64 + lq];
-        const int idx = select_lowest_max<double, WS, QPL>(m, TIE_REL, lane);
+        // Fast path: a key per frequency from the upper word of its FP64
+        // metric (sign, exponent, 20 mantissa bits; the lowest 4 replaced by
+        // the frequency's in-lane code 4t + c), the lane's largest and
+        // second-largest key and the wavefront maximum. The keys keep the
+        // metric to 2^-16 relative, so when exactly one key reaches (1 - 1e-4)
+        // of the maximum, its frequency is the FP64 maximum and no other
+        // metric lies within TIE_REL of it: the tie rule would pick the same.
+        // Otherwise (ties, near ties, all metrics zero) the exact rule decides.
+        int idx;
+        {
+            unsigned kb = 0u, ks = 0u;
+#pragma unroll
+            for (int t = 0; t < QPL; ++t) {
+                unsigned key[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    key[c] = ((unsigned)__double2hiint(m[t][c]) & ~15u) | (unsigned)(4 * t + c);
+                ks = max(ks, umed3(kb, key[0], key[1]));
+                kb = umax3(kb, key[0], key[1]);
+                ks = max(ks, umed3(kb, key[2], key[3]));
+                kb = umax3(kb, key[2], key[3]);
+            }
+            const unsigned M = wave_max_u32(kb);
+            const unsigned thr = (unsigned)__double2hiint(__hiloint2double((int)(M & ~15u), 0) * (1.0 - 1e-4));
+            const unsigned long long hi1 = __ballot(kb >= thr);
+            const unsigned long long hi2 = __ballot(ks >= thr);
+            if (__popcll(hi1) == 1 && hi2 == 0ull) {
+                const int L = __builtin_ctzll(hi1);
+                const int code = (int)(M & 15u);
+                const int t = code >> 2, a = (code >> 1) & 1, b = code & 1;
+                idx = ((L / WS) + KSTEP * t + WS * a) * W + (L % WS) + WS * b;
+            } else {
+                idx = select_lowest_max<double, WS, QPL>(m, TIE_REL, lane);
+            }
+        }
         const int u = idx / W, v = idx % W;
 
         // eq. (17) needs column (u, v) of C: start its loads now
