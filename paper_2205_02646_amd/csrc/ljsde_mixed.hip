@@ -65,9 +65,18 @@ struct MixedLds {
     static constexpr size_t offTab = offTw + (size_t)QPL * 64 * 16;
     static constexpr size_t offSlot = offTab + (size_t)(2 * WS + 2 * W) * 8;
     static constexpr size_t shared_bytes = offSlot + 64;
-    // per wavefront: DFT stage [NPOS] complex double, w*y [NPOS] double, codes [NPOS]
-    static constexpr size_t wave_bytes = (size_t)NPOS * 16 + (size_t)NPOS * 8 + NPOS;
-    static constexpr size_t bytes(int nw) { return shared_bytes + nw * wave_bytes; }
+    // per wavefront: w*y [NPOS] double and codes [NPOS] (after the prologue:
+    // the kept picks, [NPOS / 2] complex steps and [NPOS / 2] int16
+    // frequencies), then, for the window DFTs that pass a stage through LDS
+    // (the VALU passes, which W = 16 always takes, and the split-BF16
+    // products), the stage [NPOS] complex double
+    static constexpr size_t offCodes = (size_t)NPOS * 8;
+    static constexpr size_t offStage = (size_t)NPOS * 9;
+    static constexpr bool has_stage(bool vdft_or_bf16) { return WS != 16 || vdft_or_bf16; }
+    static constexpr size_t wave_bytes(bool vdft_or_bf16) {
+        return offStage + (has_stage(vdft_or_bf16) ? (size_t)NPOS * 16 : 0);
+    }
+    static constexpr size_t bytes(int nw, bool vdft_or_bf16) { return shared_bytes + nw * wave_bytes(vdft_or_bf16); }
 };
 
 // Launch-variant knobs of the FP32 kernels (picked by the autotuner):
@@ -98,15 +107,16 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
     const double *dft = tab;           // [WS][2] exp(-2 pi i k / WS)
     const double *ew = tab + 2 * WS;   // [W][2]  exp(+2 pi i k / W)
 
-    const int cls = j.rowcls[bi] * j.ncolk + j.colcls[bj];
+    // wave-uniform: the class's table bases stay in scalar registers
+    const int cls = __builtin_amdgcn_readfirstlane(j.rowcls[bi] * j.ncolk + j.colcls[bj]);
     const unsigned char *tb = j.tables + (size_t)cls * p.lay.stride;
     const double *qD64 = (const double *)(tb + p.lay.offQD64);
     const double *invD = (const double *)(tb + p.lay.offInvD);
     const signed char *codes = (const signed char *)(tb + p.lay.offCodes);
 
-    C2<double> *stage = (C2<double> *)wlds;
-    double *X = (double *)(wlds + NPOS * 16);
-    signed char *Cd = (signed char *)(wlds + NPOS * 24);
+    double *X = (double *)wlds;
+    signed char *Cd = (signed char *)(wlds + LL::offCodes);
+    C2<double> *stage = (C2<double> *)(wlds + LL::offStage);  // VALU and split-BF16 DFTs only
 
     wave_lds_fence();
 
@@ -183,21 +193,25 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
     const CDouble *invDs = (const CDouble *)invD;
 
     const int BB = p.B * p.B;  // 16 or 64: divides the wavefront
-    const int oi = lane / p.B, oj = lane % p.B;
     double outacc = 0.0;
     double E = e0;
     int nu_done = 0;
     // Eq. (18) over the picks kept so far (their coefficient step and
-    // frequency, in this wavefront's DFT stage, free after the prologue): lane
-    // L sums output pixel L % BB over picks L / BB, L / BB + 64 / BB, ...; the
-    // parts of a pixel are then added across the lanes BB apart.
-    C2<double> *pk = stage;
-    int *pidx = (int *)X;
-    constexpr int PCAP = NPOS;
+    // frequency, in this wavefront's w*y and code arrays, free after the
+    // prologue): lane L sums output pixel L % BB over picks L / BB,
+    // L / BB + 64 / BB, ...; the parts of a pixel are then added across the
+    // lanes BB apart.
+    C2<double> *pk = (C2<double> *)X;
+    int16_t *pidx = (int16_t *)Cd;
+    constexpr int PCAP = NPOS / 2;
     int npk = 0;
-    const int xo = p.off + (lane % BB) / p.B, yo = p.off + (lane % BB) % p.B;
     auto add_picks = [&]() {
         wave_lds_fence();
+        // the output pixel's coordinates, recomputed here (this runs once or a
+        // few times per window) rather than held in registers through the loop
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        const int xo = p.off + (ln % BB) / p.B, yo = p.off + (ln % BB) % p.B;
         double acc = 0.0;
         for (int k = lane / BB; k < npk; k += 64 / BB) {
             const int f = pidx[k];
@@ -224,13 +238,9 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         // eq. (11) in FP32 for the lane's frequencies; per-lane largest and
         // second-largest key (metric bits, in-lane code in the low 4 bits)
         unsigned kb = 0u, ks = 0u;
-        // per-lane q/D and twiddles of a position are read one position
-        // ahead, so their LDS latency overlaps the previous position's work
-        float4 q4n, t4n;
-        if constexpr (!QREG) {
-            q4n = *(const float4 *)(qdl + lane * 4);
-            t4n = *(const float4 *)(twl + lane * 4);
-        }
+        // per-lane q/D and twiddles of a position are read from LDS as the
+        // position is projected (no read-ahead: its registers are worth more
+        // as room for a fourth wavefront per SIMD, which hides the latency)
 #pragma unroll
         for (int t = 0; t < QPL; ++t) {
             float4 q4, t4;
@@ -238,12 +248,8 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
                 q4 = q4r[t];
                 t4 = t4r[t];
             } else {
-                q4 = q4n;
-                t4 = t4n;
-                if (t + 1 < QPL) {
-                    q4n = *(const float4 *)(qdl + ((t + 1) * 64 + lane) * 4);
-                    t4n = *(const float4 *)(twl + ((t + 1) * 64 + lane) * 4);
-                }
+                q4 = *(const float4 *)(qdl + (t * 64 + lane) * 4);
+                t4 = *(const float4 *)(twl + (t * 64 + lane) * 4);
             }
             C2<float> Pf[4], R[4];
 #pragma unroll
@@ -276,22 +282,26 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
             const int t = code >> 2, a = (code >> 1) & 1, b = code & 1;
             idx = ((L / WS) + KSTEP * t + WS * a) * W + (L % WS) + WS * b;
         } else {
-            // near tie: decide in FP64 from the FP64 state
+            // near tie: decide in FP64 from the FP64 state. The lane index is
+            // made opaque here, so that none of this (rare) branch's
+            // addressing is computed ahead of the loop and kept in registers.
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
+            const int krow_t = ln / WS, lam_t = ln % WS;
             double b0 = -1.0, b1 = -1.0;
             int i0 = 0, i1 = 0;
 #pragma unroll
             for (int t = 0; t < QPL; ++t) {
-                const int kap = krow + KSTEP * t;
+                const int kap = krow_t + KSTEP * t;
                 const C2<double> dtk = {ew[2 * kap], -ew[2 * kap + 1]};
-                const C2<double> dtkl = {ew[2 * (kap + lam)], -ew[2 * (kap + lam) + 1]};
-                const C2<double> dtl = {ew[2 * lam], -ew[2 * lam + 1]};
+                const C2<double> dtkl = {ew[2 * (kap + lam_t)], -ew[2 * (kap + lam_t) + 1]};
+                const C2<double> dtl = {ew[2 * lam_t], -ew[2 * lam_t + 1]};
                 C2<double> R[4];
                 project4<double, SHAPE>(P[t], dtl, dtk, dtkl, R);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const int a = c >> 1, b = c & 1;
-                    int f = (kap + WS * a) * W + lam + WS * b;
-                    asm volatile("" : "+v"(f));  // keep the (rare) table addressing inside this branch
+                    const int f = (kap + WS * a) * W + lam_t + WS * b;
                     const double m = (R[c].re * R[c].re + R[c].im * R[c].im) * qD64[f];
                     if (a == 0) tie_keep<double>(b0, i0, m, f, TIE_REL);
                     else tie_keep<double>(b1, i1, m, f, TIE_REL);
@@ -339,14 +349,24 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         // eqs. (15)-(16), and the energy of eq. (8) where a floor is set, FP64
         const double id = invDs[idx];
         const double gr = p.gamma * id * rr, gi = p.gamma * id * ri;
-        if (p.tau > 0.0) E = uniform_f64(E - p.ecoef * (rr * rr + ri * ri) * id);
+        bool stop = false;
+        if (p.tau > 0.0) {
+            E = uniform_f64(E - p.ecoef * (rr * rr + ri * ri) * id);
+            stop = E <= uniform_f64(p.tau * e0);
+        }
         // the spectra of the first orientation of the update, at the lane's
         // shifted positions, are read from LDS now, so that their latency
         // overlaps the pick record and the stopping test
-        const C2<double> *Sc = (const C2<double> *)Sl + ((lam - lv) & (WS - 1));
+        // lane coordinates recomputed here (the lane index from the
+        // execution mask's bit count, then two instructions) rather than held
+        // in registers through the loop
+        int lnu;
+        asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(lnu));
+        const int krow_u = lnu / WS, lam_u = lnu % WS;
+        const C2<double> *Sc = (const C2<double> *)Sl + ((lam_u - lv) & (WS - 1));
         int srow[QPL];
 #pragma unroll
-        for (int t = 0; t < QPL; ++t) srow[t] = ((krow + KSTEP * t - ku) & (WS - 1)) * WS;
+        for (int t = 0; t < QPL; ++t) srow[t] = ((krow_u + KSTEP * t - ku) & (WS - 1)) * WS;
         C2<double> sn[QPL];
 #pragma unroll
         for (int t = 0; t < QPL; ++t) sn[t] = Sc[srow[t]];
@@ -355,12 +375,12 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         // picks when the stage is full and after the last iteration
         if (lane == 0) {
             pk[npk] = {gr, gi};
-            pidx[npk] = idx;
+            pidx[npk] = (int16_t)idx;
         }
         if (++npk == PCAP) add_picks();
         if (j.sel != nullptr && lane == 0) ((GInt16 *)j.sel)[win_local * p.iters + nu] = (int16_t)idx;
         nu_done = nu + 1;
-        if (p.tau > 0.0 && E <= p.tau * e0) break;
+        if (stop) break;
         if (nu + 1 == p.iters) break;
 
         // eq. (17), factorised: P_o(k, l) -= g_o S_o(k - u, l - v) with
@@ -371,11 +391,7 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         for (int o = 0; o < 4; ++o) {
             C2<double> so[QPL];
 #pragma unroll
-            for (int t = 0; t < QPL; ++t) so[t] = sn[t];
-            if (o + 1 < 4) {
-#pragma unroll
-                for (int t = 0; t < QPL; ++t) sn[t] = Sc[(o + 1) * NPOS + srow[t]];
-            }
+            for (int t = 0; t < QPL; ++t) so[t] = o == 0 ? sn[t] : Sc[o * NPOS + srow[t]];
             const double gre = fma(gr, Hr[o], -gi * Hi[o]), gim = fma(gr, Hi[o], gi * Hr[o]);
 #pragma unroll
             for (int t = 0; t < QPL; ++t) {
@@ -389,6 +405,7 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         for (int nu = nu_done + lane; nu < p.iters; nu += 64) j.sel[win_local * p.iters + nu] = -1;
     if (lane < BB) {
         float *O = (float *)j.out;
+        const int oi = lane / p.B, oj = lane % p.B;
         const size_t row = (size_t)(p.B * bi + oi);
         O[row * (size_t)(2 * j.Ns) + (size_t)(p.B * bj + oj)] = (float)outacc;
     }
@@ -459,14 +476,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void mi
 // the class tables are staged into LDS only when the class changes. Every
 // group index is claimed exactly once whatever the actual placement.
 template <int WS, int NW, bool BF16, int SHAPE, bool QREG, bool VDFT>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(QREG ? 2 : 3))) void mixed_persistent_kernel(
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(QREG ? 2 : (VDFT || BF16) ? 3 : 4))) void
+mixed_persistent_kernel(
     KParams p, const KJob *__restrict__ jobs, const WinGroup *__restrict__ groups, const int *__restrict__ range_begin,
     unsigned int *counters, int chunk) {
     extern __shared__ __align__(16) char lds[];
     using L = MixedLds<WS>;
     int *slot = (int *)(lds + L::offSlot);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    char *wl = lds + L::shared_bytes + (size_t)wave * L::wave_bytes;
+    char *wl = lds + L::shared_bytes + (size_t)wave * L::wave_bytes(VDFT || BF16);
     const int home = (int)(blockIdx.x % XCD_RANGES);
     int tried = 0;             // ranges found exhausted (thread 0 only)
     int next = 0, left = 0;    // the current claim (thread 0 only)
@@ -516,13 +534,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(QREG ? 
     }
 }
 
-size_t mixed_lds_bytes(int ws, int nw) { return ws == 16 ? MixedLds<16>::bytes(nw) : MixedLds<8>::bytes(nw); }
+size_t mixed_lds_bytes(int ws, int nw, bool bf16) {
+    return ws == 16 ? MixedLds<16>::bytes(nw, bf16) : MixedLds<8>::bytes(nw, bf16);
+}
 
 template <int SHAPE>
 static int launch_mw(const KParams &p, const KJob &job, int ws, void *stream) {
     const long long nwin = (long long)job.nbi * job.nbj;
     if (nwin <= 0) return 0;
-    const size_t lds = mixed_lds_bytes(ws, 1);
+    const size_t lds = mixed_lds_bytes(ws, 1, p.dft_bf16 != 0);
     const dim3 grid((unsigned)nwin), block(64);
     if (ws == 16 && p.dft_bf16 && SHAPE == SHAPE_THREE_QUARTER)
         mixed_window_kernel<16, true, SHAPE_THREE_QUARTER><<<grid, block, lds, (hipStream_t)stream>>>(p, job);
@@ -543,7 +563,7 @@ int launch_mixed_window(const KParams &p, const KJob &job, int ws, void *stream)
 template <int WS, int NW, bool BF16, int SHAPE, bool QREG, bool VDFT>
 static int launch_mp(const KParams &p, const KJob *d_jobs, const WinGroup *d_groups, const int *range_begin,
                      unsigned int *counters, int chunk, int grid, void *stream) {
-    const size_t lds = MixedLds<WS>::bytes(NW);
+    const size_t lds = MixedLds<WS>::bytes(NW, VDFT || BF16);
     mixed_persistent_kernel<WS, NW, BF16, SHAPE, QREG, VDFT><<<dim3(grid), dim3(64 * NW), lds, (hipStream_t)stream>>>(
         p, d_jobs, d_groups, range_begin, counters, chunk);
     return (int)hipGetLastError();
@@ -596,7 +616,7 @@ template <int WS, int NW, bool QREG, bool VDFT>
 static int occ_mp(int *blocks) {
     return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(
         blocks, mixed_persistent_kernel<WS, NW, false, SHAPE_THREE_QUARTER, QREG, VDFT>, 64 * NW,
-        MixedLds<WS>::bytes(NW));
+        MixedLds<WS>::bytes(NW, VDFT));
 }
 
 template <bool QREG, bool VDFT>
