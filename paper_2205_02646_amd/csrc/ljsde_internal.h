@@ -105,7 +105,6 @@ int launch_dense_c_build(const KParams &p, const unsigned char *tables, int n_cl
 // f32io: float measurements and output (FP32 plans), else double.
 int launch_dense(const KParams &p, const KJob &job, const void *C, const int *order, int order_len, int ws,
                  bool f32io, void *stream);
-size_t mixed_lds_bytes(int ws, int nw, bool bf16);
 
 // Plain L-JSDE (ljsde_lplain.hip): up to LGROUP windows of one class per
 // workgroup. `count` 0 marks an idle workgroup.

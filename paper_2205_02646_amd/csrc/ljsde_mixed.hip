@@ -534,7 +534,7 @@ mixed_persistent_kernel(
     }
 }
 
-size_t mixed_lds_bytes(int ws, int nw, bool bf16) {
+static size_t mixed_lds_bytes(int ws, int nw, bool bf16) {
     return ws == 16 ? MixedLds<16>::bytes(nw, bf16) : MixedLds<8>::bytes(nw, bf16);
 }
 
