@@ -79,6 +79,16 @@ struct MixedLds {
     static constexpr size_t bytes(int nw, bool vdft_or_bf16) { return shared_bytes + nw * wave_bytes(vdft_or_bf16); }
 };
 
+// The lane index, derived afresh where it is used (the count of execution-mask
+// bits below the lane). The asm is volatile, so nothing computed from it is
+// evaluated ahead of the iteration loop and carried through it in registers
+// (at four wavefronts per SIMD such values are spilled to scratch memory).
+__device__ __forceinline__ int fresh_lane() {
+    int l;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+    return l;
+}
+
 // Launch-variant knobs of the FP32 kernels (picked by the autotuner):
 //  QREG  the per-lane q/D and projection twiddles of the window's class are
 //        loaded from LDS into registers once per window (more VGPRs, fewer
@@ -124,7 +134,7 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
     const int rs = (p.B * bi - p.off) / 2;
     const int cs = (p.B * bj - p.off) / 2;
     double e0 = 0.0;
-    for (int m = lane; m < NPOS; m += 64) {
+    for (int m = fresh_lane(); m < NPOS; m += 64) {
         const int ip = m / WS, jp = m % WS;
         const int gi = rs + ip, gj = cs + jp;
         signed char code = codes[m];
@@ -187,7 +197,8 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         }
     }
 
-    const C2<float> tl = {(float)ew[2 * lam], (float)-ew[2 * lam + 1]};
+    const int lam_l = fresh_lane() % WS;
+    const C2<float> tl = {(float)ew[2 * lam_l], (float)-ew[2 * lam_l + 1]};
     // the L-pixel response table, read with wave-uniform indices: scalar loads
     const CDouble *Ht = (const CDouble *)p.c.H;
     const CDouble *invDs = (const CDouble *)invD;
@@ -209,11 +220,10 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         wave_lds_fence();
         // the output pixel's coordinates, recomputed here (this runs once or a
         // few times per window) rather than held in registers through the loop
-        int ln = lane;
-        asm volatile("" : "+v"(ln));
+        const int ln = fresh_lane();
         const int xo = p.off + (ln % BB) / p.B, yo = p.off + (ln % BB) % p.B;
         double acc = 0.0;
-        for (int k = lane / BB; k < npk; k += 64 / BB) {
+        for (int k = ln / BB; k < npk; k += 64 / BB) {
             const int f = pidx[k];
             const C2<double> g = pk[k];
             const int ph = (xo * (f / W) + yo * (f % W)) & (W - 1);
@@ -283,10 +293,9 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
             idx = ((L / WS) + KSTEP * t + WS * a) * W + (L % WS) + WS * b;
         } else {
             // near tie: decide in FP64 from the FP64 state. The lane index is
-            // made opaque here, so that none of this (rare) branch's
+            // derived afresh here, so that none of this (rare) branch's
             // addressing is computed ahead of the loop and kept in registers.
-            int ln = lane;
-            asm volatile("" : "+v"(ln));
+            const int ln = fresh_lane();
             const int krow_t = ln / WS, lam_t = ln % WS;
             double b0 = -1.0, b1 = -1.0;
             int i0 = 0, i1 = 0;
@@ -357,11 +366,9 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         // the spectra of the first orientation of the update, at the lane's
         // shifted positions, are read from LDS now, so that their latency
         // overlaps the pick record and the stopping test
-        // lane coordinates recomputed here (the lane index from the
-        // execution mask's bit count, then two instructions) rather than held
-        // in registers through the loop
-        int lnu;
-        asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(lnu));
+        // lane coordinates recomputed here (a fresh lane index, then two
+        // instructions) rather than held in registers through the loop
+        const int lnu = fresh_lane();
         const int krow_u = lnu / WS, lam_u = lnu % WS;
         const C2<double> *Sc = (const C2<double> *)Sl + ((lam_u - lv) & (WS - 1));
         int srow[QPL];
@@ -401,11 +408,12 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         }
     }
     if (npk > 0) add_picks();
+    const int lo = fresh_lane();
     if (j.sel != nullptr)
-        for (int nu = nu_done + lane; nu < p.iters; nu += 64) j.sel[win_local * p.iters + nu] = -1;
-    if (lane < BB) {
+        for (int nu = nu_done + lo; nu < p.iters; nu += 64) j.sel[win_local * p.iters + nu] = -1;
+    if (lo < BB) {
         float *O = (float *)j.out;
-        const int oi = lane / p.B, oj = lane % p.B;
+        const int oi = lo / p.B, oj = lo % p.B;
         const size_t row = (size_t)(p.B * bi + oi);
         O[row * (size_t)(2 * j.Ns) + (size_t)(p.B * bj + oj)] = (float)outacc;
     }
