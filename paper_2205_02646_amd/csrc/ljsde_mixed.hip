@@ -106,10 +106,9 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
     constexpr int W = 2 * WS;
     constexpr int QPL = WS * WS / 64;
     constexpr int NPOS = WS * WS;
-    int lane = threadIdx.x & 63;
-    // opaque per window: stops lane-derived addressing from being hoisted out
+    // derived per window: keeps lane-derived addressing from being hoisted out
     // of the persistent loop and kept live (in VGPRs) across all windows
-    asm volatile("" : "+v"(lane));
+    const int lane = fresh_lane();
     // lane L owns the positions k = L / WS + KSTEP t (t < QPL), l = L % WS
     constexpr int KSTEP = 64 / WS;
     const int lam = lane % WS;
@@ -204,6 +203,7 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
     const CDouble *invDs = (const CDouble *)invD;
 
     const int BB = p.B * p.B;  // 16 or 64: divides the wavefront
+    const int lgB = p.B == 8 ? 3 : 2;  // the block side is 4 or 8
     double outacc = 0.0;
     double E = e0;
     int nu_done = 0;
@@ -221,9 +221,9 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         // the output pixel's coordinates, recomputed here (this runs once or a
         // few times per window) rather than held in registers through the loop
         const int ln = fresh_lane();
-        const int xo = p.off + (ln % BB) / p.B, yo = p.off + (ln % BB) % p.B;
+        const int xo = p.off + ((ln & (BB - 1)) >> lgB), yo = p.off + (ln & (p.B - 1));
         double acc = 0.0;
-        for (int k = ln / BB; k < npk; k += 64 / BB) {
+        for (int k = ln >> (2 * lgB); k < npk; k += 64 / BB) {
             const int f = pidx[k];
             const C2<double> g = pk[k];
             const int ph = (xo * (f / W) + yo * (f % W)) & (W - 1);
@@ -361,7 +361,12 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         bool stop = false;
         if (p.tau > 0.0) {
             E = uniform_f64(E - p.ecoef * (rr * rr + ri * ri) * id);
-            stop = E <= uniform_f64(p.tau * e0);
+            // the floor is formed here, from an opaque copy of e0, so that it
+            // is not computed ahead and carried through the loop in vector
+            // registers (which would spill at four wavefronts per SIMD)
+            double e0c = e0;
+            asm volatile("" : "+v"(e0c));
+            stop = E <= uniform_f64(p.tau * e0c);
         }
         // the spectra of the first orientation of the update, at the lane's
         // shifted positions, are read from LDS now, so that their latency
@@ -413,7 +418,7 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         for (int nu = nu_done + lo; nu < p.iters; nu += 64) j.sel[win_local * p.iters + nu] = -1;
     if (lo < BB) {
         float *O = (float *)j.out;
-        const int oi = lo / p.B, oj = lo % p.B;
+        const int oi = lo >> lgB, oj = lo & (p.B - 1);
         const size_t row = (size_t)(p.B * bi + oi);
         O[row * (size_t)(2 * j.Ns) + (size_t)(p.B * bj + oj)] = (float)outacc;
     }
