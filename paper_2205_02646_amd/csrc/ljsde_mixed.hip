@@ -245,6 +245,13 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
 
 #pragma unroll 1
     for (int nu = 0; nu < p.iters; ++nu) {
+        // Issue priority among the wavefronts of a SIMD rises with the
+        // progress through an iteration: the projection at 0, the dependent
+        // chain from the wave maximum to the step (reductions, readlanes, the
+        // table reads that wait for the pick, little to overlap) at 2, the
+        // rest of the iteration and the update at 1. Wavefronts in the bulk
+        // work fill the gaps of the one in its chain.
+        __builtin_amdgcn_s_setprio(0);
         // eq. (11) in FP32 for the lane's frequencies; per-lane largest and
         // second-largest key (metric bits, in-lane code in the low 4 bits)
         unsigned kb = 0u, ks = 0u;
@@ -279,10 +286,6 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
             kb = umax3(kb, key[2], key[3]);
             __builtin_amdgcn_sched_barrier(0);  // one position at a time: bounds register pressure
         }
-        // From the wave maximum to the step the wavefront runs one dependent
-        // chain with little to overlap (reductions, readlanes, the table reads
-        // that wait for the pick): it takes issue priority over the other
-        // wavefronts of its SIMD, whose projections and updates fill the gaps.
         __builtin_amdgcn_s_setprio(2);
         // The FP32 winner stands when no other key reaches (1 - NEAR_TIE) of
         // it: exactly one lane's best and no lane's second are at or above it.
@@ -363,7 +366,7 @@ __device__ __forceinline__ void process_window_mixed(const KParams &p, const KJo
         // eqs. (15)-(16), and the energy of eq. (8) where a floor is set, FP64
         const double id = invDs[idx];
         const double gr = p.gamma * id * rr, gi = p.gamma * id * ri;
-        __builtin_amdgcn_s_setprio(0);
+        __builtin_amdgcn_s_setprio(1);
         bool stop = false;
         if (p.tau > 0.0) {
             E = uniform_f64(E - p.ecoef * (rr * rr + ri * ri) * id);
