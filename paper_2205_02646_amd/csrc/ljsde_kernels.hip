@@ -104,6 +104,10 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
 
 #pragma unroll 1
     for (int nu = 0; nu < p.iters; ++nu) {
+        // issue priority: the update and projection at 0, the dependent chain
+        // from the selection to the step at 2, so that of the wavefronts of a
+        // SIMD the one in that chain issues first
+        __builtin_amdgcn_s_setprio(0);
         T m[QPL][4];
 #pragma unroll
         for (int t = 0; t < QPL; ++t) {
@@ -141,6 +145,7 @@ __device__ __forceinline__ void process_window(const KParams &p, const KJob &j, 
             m[t][3] = (r11.re * r11.re + r11.im * r11.im) * qd[t][3];
         }
         // first maximum in sigma * W + rho order (within the tie band)
+        __builtin_amdgcn_s_setprio(2);
         const int idx = select_lowest_max<T, WS, QPL>(m, eps, lane);
         u = idx / W;
         v = idx % W;
