@@ -31,26 +31,40 @@ typedef const double __attribute__((address_space(4))) CDouble;
 // holds up the waits on LDS reads.
 typedef int16_t __attribute__((address_space(1))) GInt16;
 
-// R(a, b) of one position in FP32: the same linear map as project4, with
-// the per-quadrant sums of three-quarter sampling taken from two pair sums
-// (each Q_q adds the three orientations other than q: 12 operations instead
-// of 14). Folding the twiddle products into the Walsh-Hadamard additions as
-// fused multiply-adds (with the differences taken as 2 x - s) saves 4 more
-// operations per position but runs slower on gfx950: the three-operand
-// instructions and the longer dependency chains cost more than the additions
-// they replace.
+// R(a, b) of one position in FP32: the same linear map as project4. The
+// per-quadrant sums of three-quarter sampling come from two pair sums (each
+// Q_q adds the three orientations other than q: 12 operations instead of 14),
+// and the twiddle products are folded into the 2 x 2 Walsh-Hadamard step as
+// fused multiply-adds, the differences taken as 2 x - s:
+//   s1 = Q_0 + t_kl Q_3, d1 = 2 Q_0 - s1; u1 = t_l Q_1, s2 = u1 + t_k Q_2,
+//   d2 = 2 u1 - s2; R = (s1 + s2, d1 - d2, d1 + d2, s1 - s2).
+// 36 operations per position instead of 40, in longer dependency chains
+// (the FP32 search's error test replays exactly this order).
 template <int SHAPE>
 __device__ __forceinline__ void project4_f32(const C2<float> P[4], C2<float> tl, C2<float> tk, C2<float> tkl,
                                              C2<float> R[4]) {
+    C2<float> Q[4];
     if constexpr (SHAPE == SHAPE_THREE_QUARTER) {
         const C2<float> a = {P[0].re + P[1].re, P[0].im + P[1].im};
         const C2<float> b = {P[2].re + P[3].re, P[2].im + P[3].im};
-        const C2<float> Q[4] = {{P[1].re + b.re, P[1].im + b.im}, {P[0].re + b.re, P[0].im + b.im},
-                                {a.re + P[3].re, a.im + P[3].im}, {a.re + P[2].re, a.im + P[2].im}};
-        project4<float, SHAPE_QUARTER>(Q, tl, tk, tkl, R);  // the twiddled 2 x 2 step on Q
+        Q[0] = {P[1].re + b.re, P[1].im + b.im};
+        Q[1] = {P[0].re + b.re, P[0].im + b.im};
+        Q[2] = {a.re + P[3].re, a.im + P[3].im};
+        Q[3] = {a.re + P[2].re, a.im + P[2].im};
     } else {
-        project4<float, SHAPE>(P, tl, tk, tkl, R);
+        shape_sums<SHAPE, float>(P, Q);
     }
+    const C2<float> s1 = {fmaf(tkl.re, Q[3].re, fmaf(-tkl.im, Q[3].im, Q[0].re)),
+                          fmaf(tkl.re, Q[3].im, fmaf(tkl.im, Q[3].re, Q[0].im))};
+    const C2<float> d1 = {fmaf(2.0f, Q[0].re, -s1.re), fmaf(2.0f, Q[0].im, -s1.im)};
+    const C2<float> u1 = {fmaf(tl.re, Q[1].re, -tl.im * Q[1].im), fmaf(tl.re, Q[1].im, tl.im * Q[1].re)};
+    const C2<float> s2 = {fmaf(tk.re, Q[2].re, fmaf(-tk.im, Q[2].im, u1.re)),
+                          fmaf(tk.re, Q[2].im, fmaf(tk.im, Q[2].re, u1.im))};
+    const C2<float> d2 = {fmaf(2.0f, u1.re, -s2.re), fmaf(2.0f, u1.im, -s2.im)};
+    R[0] = {s1.re + s2.re, s1.im + s2.im};  // (a, b) = (0, 0)
+    R[1] = {d1.re - d2.re, d1.im - d2.im};  // (0, 1)
+    R[2] = {d1.re + d2.re, d1.im + d2.im};  // (1, 0)
+    R[3] = {s1.re - s2.re, s1.im - s2.im};  // (1, 1)
 }
 
 template <int WS>

@@ -9,11 +9,11 @@ in FP64). This test replays that arithmetic on the CPU: an FP64 recurrent loop
 in the factorised form (its selection sequences are checked against the
 oracle's), and at every iteration the FP32 evaluation of all W^2 metrics from
 the FP64 state, in the kernel's order of operations (rounding of P to float32,
-the per-quadrant sums from two pair sums, the twiddle products with the
-compiler's contraction (re = fma(t_re, q_re, -(t_im q_im)), im = fma(t_re,
-q_im, t_im q_re)), the 2 x 2 Walsh-Hadamard step, |R|^2 q / D with q / D
-rounded to float32, the four low bits of the key replaced by the frequency
-code). A fused multiply-add is replayed as the exact product and sum in
+the per-quadrant sums from two pair sums, the twiddle products folded into
+the 2 x 2 Walsh-Hadamard step as fused multiply-adds (s1 = Q_0 + t_kl Q_3,
+d1 = 2 Q_0 - s1, u1 = t_l Q_1, s2 = u1 + t_k Q_2, d2 = 2 u1 - s2), |R|^2 q / D
+with q / D rounded to float32, the four low bits of the key replaced by the
+frequency code). A fused multiply-add is replayed as the exact product and sum in
 float64, rounded once more to float32. It asserts that every accepted FP32 decision
 equals the FP64 decision, and measures the largest FP32 metric error relative
 to the maximum metric among the candidates within 1e-3 of it: the guard's
@@ -70,16 +70,12 @@ def _fp32_keys(P, qd32, shape):
     ckl = np.cos(THETA * (k[:, None] + k[None, :])).astype(f32)
     skl = (-np.sin(THETA * (k[:, None] + k[None, :]))).astype(f32)
 
-    def cmul(tr, ti, qr, qi):
-        return fma(tr, qr, -(ti * qi)), fma(tr, qi, ti * qr)
-
-    u1 = cmul(cl, sl, Qr[1], Qi[1])
-    u2 = cmul(ck, sk, Qr[2], Qi[2])
-    u3 = cmul(ckl, skl, Qr[3], Qi[3])
-    s1 = (Qr[0] + u3[0], Qi[0] + u3[1])
-    d1 = (Qr[0] - u3[0], Qi[0] - u3[1])
-    s2 = (u1[0] + u2[0], u1[1] + u2[1])
-    d2 = (u1[0] - u2[0], u1[1] - u2[1])
+    two = f32(2)
+    s1 = (fma(ckl, Qr[3], fma(-skl, Qi[3], Qr[0])), fma(ckl, Qi[3], fma(skl, Qr[3], Qi[0])))
+    d1 = (fma(two, Qr[0], -s1[0]), fma(two, Qi[0], -s1[1]))
+    u1 = (fma(cl, Qr[1], -(sl * Qi[1])), fma(cl, Qi[1], sl * Qr[1]))
+    s2 = (fma(ck, Qr[2], fma(-sk, Qi[2], u1[0])), fma(ck, Qi[2], fma(sk, Qr[2], u1[1])))
+    d2 = (fma(two, u1[0], -s2[0]), fma(two, u1[1], -s2[1]))
     R = {(0, 0): (s1[0] + s2[0], s1[1] + s2[1]), (0, 1): (d1[0] - d2[0], d1[1] - d2[1]),
          (1, 0): (d1[0] + d2[0], d1[1] + d2[1]), (1, 1): (s1[0] - s2[0], s1[1] - s2[1])}
     keys = np.zeros((W, W), dtype=f32)
